@@ -1,0 +1,157 @@
+"""ctypes wrapper of the plain CPU oracle (pedsim_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg may use this package; the library never does. It builds the
+oracle with gcc (-O2 -ffp-contract=off, plain loops, one thread) on first use
+if the shared object is missing, and `build()` rebuilds it unconditionally.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pedsim_oracle.c")
+_LIB = os.path.join(_HERE, "libpedsim_oracle.so")
+
+MODE_LEM, MODE_ACO = 0, 1
+
+
+class OracleParams(ctypes.Structure):
+    _fields_ = [
+        ("W", ctypes.c_int32), ("H", ctypes.c_int32), ("seed", ctypes.c_uint64),
+        ("rho", ctypes.c_float), ("dtau", ctypes.c_float),
+        ("alpha", ctypes.c_int32), ("beta", ctypes.c_int32),
+        ("cross_a", ctypes.c_int32), ("cross_b", ctypes.c_int32),
+    ]
+
+
+def build() -> str:
+    """Compile the oracle into oracle/libpedsim_oracle.so."""
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+           "-shared", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        L.oracle_philox4x32_10.argtypes = [P(ctypes.c_uint32), P(ctypes.c_uint32),
+                                           P(ctypes.c_uint32)]
+        L.oracle_philox4x32_10.restype = None
+        L.oracle_lem_thresholds.argtypes = [P(ctypes.c_uint32)]
+        L.oracle_heuristic_weights.argtypes = [ctypes.c_int32, P(ctypes.c_float)]
+        L.oracle_step.argtypes = [P(OracleParams), ctypes.c_int32, ctypes.c_uint64,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.oracle_step.restype = ctypes.c_int64
+        L.oracle_run.argtypes = [P(OracleParams), ctypes.c_int32, ctypes.c_uint64,
+                                 ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_void_p]
+        L.oracle_run.restype = ctypes.c_int64
+        L.oracle_counts.argtypes = [P(OracleParams), ctypes.c_void_p, P(ctypes.c_uint64)]
+        _lib = L
+    return _lib
+
+
+def philox4x32_10(ctr, key) -> Tuple[int, int, int, int]:
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().oracle_philox4x32_10(c, k, o)
+    return tuple(int(v) for v in o)
+
+
+def agent_words(seed: int, t: int, k: int):
+    """The four Philox words agent k draws in step t under `seed`."""
+    return philox4x32_10((k, t & 0xFFFFFFFF, t >> 32, 0),
+                         (seed & 0xFFFFFFFF, seed >> 32))
+
+
+def lem_thresholds():
+    o = (ctypes.c_uint32 * 3)()
+    lib().oracle_lem_thresholds(o)
+    return tuple(int(v) for v in o)
+
+
+def heuristic_weights(beta: int):
+    """(eta^beta) for the forward, diagonal and lateral candidates."""
+    o = (ctypes.c_float * 3)()
+    lib().oracle_heuristic_weights(int(beta), o)
+    return tuple(np.float32(v) for v in o)
+
+
+class State:
+    """Host copy of one scenario's planes, advanced by the oracle."""
+
+    def __init__(self, code, ids, tau=None, *, seed: int, rho: float = 0.1,
+                 dtau: float = 1.0, alpha: int = 1, beta: int = 2, cross_a: int = 1,
+                 cross_b: int = 1, t: int = 0):
+        self.code = np.ascontiguousarray(code, dtype=np.uint8).copy()
+        self.ids = np.ascontiguousarray(ids, dtype=np.uint32).copy()
+        self.H, self.W = self.code.shape
+        if tau is None:
+            self.tau = None
+        else:
+            self.tau = np.ascontiguousarray(tau, dtype=np.float32).copy()
+            assert self.tau.shape == (2, self.H, self.W)
+        self.p = OracleParams(self.W, self.H, seed, rho, dtau, alpha, beta, cross_a,
+                              cross_b)
+        self.t = t
+
+    @classmethod
+    def from_scenario(cls, s) -> "State":
+        return cls(s.code, s.ids, s.tau, seed=s.seed, rho=s.rho, dtau=s.dtau,
+                   alpha=s.alpha, beta=s.beta, cross_a=s.cross_a, cross_b=s.cross_b)
+
+    def _tau_ptrs(self, mode):
+        if mode == MODE_ACO:
+            if self.tau is None:
+                raise ValueError("ACO step needs pheromone planes")
+            return self.tau[0].ctypes.data, self.tau[1].ctypes.data
+        return None, None
+
+    def step(self, mode: int, want_detail: bool = False):
+        """One step; returns moved, or (moved, req, win) with want_detail."""
+        ta, tb = self._tau_ptrs(mode)
+        req = win = None
+        if want_detail:
+            req = np.zeros((self.H, self.W), dtype=np.uint8)
+            win = np.zeros((self.H, self.W), dtype=np.uint8)
+        moved = lib().oracle_step(ctypes.byref(self.p), mode, self.t, self.code.ctypes.data,
+                                  self.ids.ctypes.data, ta, tb,
+                                  None if req is None else req.ctypes.data,
+                                  None if win is None else win.ctypes.data)
+        if moved < 0:
+            raise MemoryError("oracle step failed to allocate")
+        self.t += 1
+        return (moved, req, win) if want_detail else moved
+
+    def run(self, mode: int, nsteps: int) -> int:
+        ta, tb = self._tau_ptrs(mode)
+        moved = lib().oracle_run(ctypes.byref(self.p), mode, self.t, nsteps,
+                                 self.code.ctypes.data, self.ids.ctypes.data, ta, tb)
+        if moved < 0:
+            raise MemoryError("oracle step failed to allocate")
+        self.t += nsteps
+        return moved
+
+    def counts(self):
+        """(agents_a, agents_b, crossed_a, crossed_b)."""
+        o = (ctypes.c_uint64 * 4)()
+        lib().oracle_counts(ctypes.byref(self.p), self.code.ctypes.data, o)
+        return tuple(int(v) for v in o)

@@ -1,0 +1,401 @@
+/*
+ * Plain CPU oracle for the bi-directional pedestrian update of Dutta, McLeod
+ * and Friesen, "GPU accelerated Nature Inspired Methods for Modelling Large
+ * Scale Bi-Directional Pedestrian Movement" (arXiv 1412.4933).
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the slow, obviously correct reference
+ * that the HIP library is checked against. Only the tests, the smoke check and
+ * the benchmark's CPU-baseline leg may load it. It shares no code, header,
+ * table or constant with the HIP library.
+ *
+ * Every step follows the paper's order on the snapshot of time t:
+ *   1. request  (tour construction, Sec. III and Sec. IV.b-c): every agent
+ *      picks one target cell;
+ *   2. resolve  (scatter-to-gather, Sec. IV.d): every cell that is empty at t
+ *      looks at the neighbours that picked it and keeps exactly one;
+ *   3. commit   (Sec. IV.d): winners move, everyone else stays;
+ *   4. pheromone (ACO only; eq. 3 then eq. 4, Sec. IV.d): every cell of both
+ *      planes evaporates, then gains the deposit if its group stands on it.
+ *
+ * Readings taken where the paper is silent (each listed in the design notes):
+ *   - frame: x = column, y = row; group A (code 1) heads +x, group B (code 2)
+ *     heads -x; code 3 is a wall; outside the grid counts as wall.
+ *   - candidates: forward F=(x+d,y), forward diagonals FD-=(x+d,y-1) and
+ *     FD+=(x+d,y+1), laterals L-=(x,y-1) and L+=(x,y+1); staying is implicit.
+ *     The paper allows all eight neighbours (Sec. III); backward cells are
+ *     left out here.
+ *   - "empty" means code 0 in the snapshot of time t: a cell vacated in step
+ *     t can only be entered in step t+1.
+ *   - forward first: an empty F is taken without further calculation
+ *     (Sec. III, Sec. IV.c).
+ *   - random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with
+ *     counter (agent k, t low word, t high word, 0) and key (seed low word,
+ *     seed high word); words r0 = conflict ticket, r1 = choice, r2 = side bit.
+ *   - distance table (constant, Sec. IV.a-b): squared distance from each
+ *     candidate to the point two cells ahead: F 1, FD 2, L 5, so that F is
+ *     nearest and the two diagonals tie (Sec. IV.b). eta = 1/D, and the
+ *     heuristic weight eta^beta is the correctly rounded float of D2^(-beta/2).
+ *   - LEM (eq. 1, Sec. II.A and IV.c): the empty candidates are ranked by
+ *     distance, the two members of a symmetric pair in an order drawn from
+ *     bit 0 of r2 (set: the +y side first). z ~ N(0,1) from r1, negatives go
+ *     to 0, the index is round-half-up(z) clamped to the last candidate:
+ *     index = #{j : r1 >= T_j}, T_j = ceil(2^32 * Phi(j + 1/2)).
+ *   - ACO (eq. 2 with alpha, beta, Sec. II.B and IV.c): weights
+ *     w_i = tau_g(c_i)^alpha * eta_i^beta over [FD-, FD+, L-, L+] (0 when
+ *     the candidate is not empty), tau_g the agent's own group's plane;
+ *     roulette with u = (r1 >> 8) * 2^-24 against running float sums; when
+ *     every weight is 0 the LEM rule is used with the same words.
+ *   - conflict winner (Sec. IV.d picks one requester uniformly): the lowest
+ *     (r0, k) among the requesters.
+ *   - deposit (eq. 4 with a constant amount): dtau on every cell occupied by
+ *     the group after the commit; keep = fl(1 - rho).
+ * All float arithmetic is IEEE binary32, one operation at a time, without
+ * contraction into fused multiply-adds (built with -ffp-contract=off) and
+ * with subnormals kept.
+ */
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+#define O_EMPTY 0
+#define O_A 1
+#define O_B 2
+#define O_WALL 3
+
+/* request codes: which candidate an agent picked */
+#define O_REQ_NONE 0
+#define O_REQ_F 1
+#define O_REQ_FDM 2
+#define O_REQ_FDP 3
+#define O_REQ_LM 4
+#define O_REQ_LP 5
+
+typedef struct {
+  int32_t W, H;
+  uint64_t seed;
+  float rho, dtau;
+  int32_t alpha, beta;
+  int32_t cross_a, cross_b;
+} oracle_params;
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 from its published definition: a 4-word counter block goes */
+/* through 10 rounds; each round multiplies words 0 and 2 by two fixed odd   */
+/* constants, the high halves are xored with the other two words and the     */
+/* round key, and the words are permuted; the 2-word key is advanced by two  */
+/* Weyl constants between rounds.                                            */
+/* ------------------------------------------------------------------------ */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  const uint32_t mul0 = 0xD2511F53u, mul1 = 0xCD9E8D57u;
+  const uint32_t weyl0 = 0x9E3779B9u, weyl1 = 0xBB67AE85u;
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  int round;
+  for (round = 0; round < 10; ++round) {
+    uint64_t p0, p1;
+    uint32_t hi0, lo0, hi1, lo1;
+    if (round > 0) {
+      k0 += weyl0;
+      k1 += weyl1;
+    }
+    p0 = (uint64_t)mul0 * (uint64_t)x0;
+    p1 = (uint64_t)mul1 * (uint64_t)x2;
+    hi0 = (uint32_t)(p0 >> 32);
+    lo0 = (uint32_t)p0;
+    hi1 = (uint32_t)(p1 >> 32);
+    lo1 = (uint32_t)p1;
+    x0 = hi1 ^ x1 ^ k0;
+    x1 = lo1;
+    x2 = hi0 ^ x3 ^ k1;
+    x3 = lo0;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+/* The four words an agent draws in step t. */
+static void agent_words(uint64_t seed, uint64_t t, uint32_t k, uint32_t w[4]) {
+  uint32_t ctr[4], key[2];
+  ctr[0] = k;
+  ctr[1] = (uint32_t)t;
+  ctr[2] = (uint32_t)(t >> 32);
+  ctr[3] = 0;
+  key[0] = (uint32_t)seed;
+  key[1] = (uint32_t)(seed >> 32);
+  oracle_philox4x32_10(ctr, key, w);
+}
+
+/* LEM thresholds T_j = ceil(2^32 * Phi(j + 1/2)), j = 0, 1, 2, with Phi the
+ * standard normal CDF: Phi(0.5) = 0.69146246127..., Phi(1.5) = 0.93319279873...,
+ * Phi(2.5) = 0.99379033467... */
+static const uint32_t lem_threshold[3] = {2969808658u, 4008032552u, 4268296987u};
+
+void oracle_lem_thresholds(uint32_t out[3]) {
+  out[0] = lem_threshold[0];
+  out[1] = lem_threshold[1];
+  out[2] = lem_threshold[2];
+}
+
+/* Squared distances from a candidate to the point two cells ahead. */
+#define D2_FORWARD 1.0
+#define D2_DIAGONAL 2.0
+#define D2_LATERAL 5.0
+
+/* eta^beta = D2^(-beta/2), rounded to float. */
+static float heuristic_weight(double d2, int beta) {
+  return (float)pow(d2, -0.5 * (double)beta);
+}
+
+void oracle_heuristic_weights(int32_t beta, float out[3]) {
+  out[0] = heuristic_weight(D2_FORWARD, beta);
+  out[1] = heuristic_weight(D2_DIAGONAL, beta);
+  out[2] = heuristic_weight(D2_LATERAL, beta);
+}
+
+static int inside(const oracle_params *p, int x, int y) {
+  return x >= 0 && x < p->W && y >= 0 && y < p->H;
+}
+
+static int free_cell(const oracle_params *p, const uint8_t *code, int x, int y) {
+  if (!inside(p, x, y)) return 0;
+  return code[(size_t)y * (size_t)p->W + (size_t)x] == O_EMPTY;
+}
+
+static int heading(int group) { return group == O_A ? 1 : -1; }
+
+/* Target of request `r` for an agent at (x, y) heading d. */
+static void target_of(int r, int x, int y, int d, int *tx, int *ty) {
+  *tx = x;
+  *ty = y;
+  switch (r) {
+    case O_REQ_F: *tx = x + d; break;
+    case O_REQ_FDM: *tx = x + d; *ty = y - 1; break;
+    case O_REQ_FDP: *tx = x + d; *ty = y + 1; break;
+    case O_REQ_LM: *ty = y - 1; break;
+    case O_REQ_LP: *ty = y + 1; break;
+    default: break;
+  }
+}
+
+/* LEM choice among the side candidates, eq. (1) with the normal draw.
+ * avail[0..3] refer to FD-, FD+, L-, L+. */
+static int lem_choice(const int avail[4], uint32_t r1, uint32_t r2) {
+  static const int minus_first[4] = {O_REQ_FDM, O_REQ_FDP, O_REQ_LM, O_REQ_LP};
+  static const int plus_first[4] = {O_REQ_FDP, O_REQ_FDM, O_REQ_LP, O_REQ_LM};
+  const int *order = (r2 & 1u) ? plus_first : minus_first;
+  int ranked[4];
+  int n = 0, i, index;
+  for (i = 0; i < 4; ++i) {
+    int r = order[i];
+    if (avail[r - O_REQ_FDM]) ranked[n++] = r;
+  }
+  if (n == 0) return O_REQ_NONE;
+  index = 0;
+  for (i = 0; i < 3; ++i)
+    if (r1 >= lem_threshold[i]) index += 1;
+  if (index > n - 1) index = n - 1;
+  return ranked[index];
+}
+
+/* ACO choice among the side candidates, eq. (2): roulette on
+ * tau^alpha * eta^beta. tau[0..3] is the group's pheromone on FD-, FD+, L-, L+. */
+static int aco_choice(const int avail[4], const float tau[4], float eta_diag,
+                      float eta_lat, int alpha, uint32_t r1, uint32_t r2) {
+  float w[4];
+  float sum, u, target, running;
+  int i, last;
+  for (i = 0; i < 4; ++i) {
+    if (avail[i]) {
+      float power = 1.0f;
+      int a;
+      if (alpha > 0) {
+        power = tau[i];
+        for (a = 1; a < alpha; ++a) power = power * tau[i];
+      }
+      w[i] = power * (i < 2 ? eta_diag : eta_lat);
+    } else {
+      w[i] = 0.0f;
+    }
+  }
+  sum = w[0] + w[1];
+  sum = sum + w[2];
+  sum = sum + w[3];
+  if (sum == 0.0f) return lem_choice(avail, r1, r2);
+  u = (float)(r1 >> 8) * 0x1p-24f;
+  target = u * sum;
+  running = 0.0f;
+  last = -1;
+  for (i = 0; i < 4; ++i) {
+    running = running + w[i];
+    if (w[i] > 0.0f) {
+      last = i;
+      if (target < running) return O_REQ_FDM + i;
+    }
+  }
+  return O_REQ_FDM + last;
+}
+
+/* Request of the agent standing on (x, y) at step t. */
+static int request_of(const oracle_params *p, int mode, uint64_t t, const uint8_t *code,
+                      const uint32_t *id, const float *tau_a, const float *tau_b,
+                      float eta_diag, float eta_lat, int x, int y) {
+  size_t c = (size_t)y * (size_t)p->W + (size_t)x;
+  int g = code[c];
+  int d = heading(g);
+  int avail[4];
+  int side_x[4], side_y[4];
+  uint32_t w[4];
+  int i;
+  if (free_cell(p, code, x + d, y)) return O_REQ_F;
+  for (i = 0; i < 4; ++i) {
+    target_of(O_REQ_FDM + i, x, y, d, &side_x[i], &side_y[i]);
+    avail[i] = free_cell(p, code, side_x[i], side_y[i]);
+  }
+  if (!avail[0] && !avail[1] && !avail[2] && !avail[3]) return O_REQ_NONE;
+  agent_words(p->seed, t, id[c] - 1u, w);
+  if (mode == 0) return lem_choice(avail, w[1], w[2]);
+  {
+    const float *plane = (g == O_A) ? tau_a : tau_b;
+    float tau[4];
+    for (i = 0; i < 4; ++i)
+      tau[i] = avail[i] ? plane[(size_t)side_y[i] * (size_t)p->W + (size_t)side_x[i]] : 0.0f;
+    return aco_choice(avail, tau, eta_diag, eta_lat, p->alpha, w[1], w[2]);
+  }
+}
+
+/*
+ * One step in place. mode 0 = LEM, 1 = ACO (tau planes required).
+ * req_out (optional, H*W bytes): each agent's request code, 0 elsewhere.
+ * win_out (optional, H*W bytes): for each cell empty at t that received an
+ *   agent, 1 + (dy+1)*3 + (dx+1) where (dx, dy) points from the cell to the
+ *   winner's old cell; 0 elsewhere.
+ * Returns the number of agents that moved, or -1 on allocation failure.
+ */
+int64_t oracle_step(const oracle_params *p, int32_t mode, uint64_t t, uint8_t *code,
+                    uint32_t *id, float *tau_a, float *tau_b, uint8_t *req_out,
+                    uint8_t *win_out) {
+  const int W = p->W, H = p->H;
+  const size_t cells = (size_t)W * (size_t)H;
+  uint8_t *req = (uint8_t *)calloc(cells, 1);
+  uint8_t *new_code = (uint8_t *)malloc(cells);
+  uint32_t *new_id = (uint32_t *)malloc(cells * sizeof(uint32_t));
+  float eta_diag = heuristic_weight(D2_DIAGONAL, p->beta);
+  float eta_lat = heuristic_weight(D2_LATERAL, p->beta);
+  int64_t moved = 0;
+  int x, y;
+  if (!req || !new_code || !new_id) {
+    free(req);
+    free(new_code);
+    free(new_id);
+    return -1;
+  }
+  if (win_out) memset(win_out, 0, cells);
+
+  /* 1. request, every agent on the snapshot of time t */
+  for (y = 0; y < H; ++y)
+    for (x = 0; x < W; ++x) {
+      size_t c = (size_t)y * W + x;
+      if (code[c] == O_A || code[c] == O_B)
+        req[c] = (uint8_t)request_of(p, mode, t, code, id, tau_a, tau_b, eta_diag,
+                                     eta_lat, x, y);
+    }
+
+  /* 2.+3. resolve every cell empty at t, then commit into fresh planes */
+  memcpy(new_code, code, cells);
+  memcpy(new_id, id, cells * sizeof(uint32_t));
+  for (y = 0; y < H; ++y)
+    for (x = 0; x < W; ++x) {
+      size_t c = (size_t)y * W + x;
+      int dx, dy, have = 0, best_dx = 0, best_dy = 0;
+      uint32_t best_ticket = 0, best_k = 0;
+      if (code[c] != O_EMPTY) continue;
+      for (dy = -1; dy <= 1; ++dy)
+        for (dx = -1; dx <= 1; ++dx) {
+          int nx = x + dx, ny = y + dy, tx, ty;
+          size_t n;
+          if ((dx == 0 && dy == 0) || !inside(p, nx, ny)) continue;
+          n = (size_t)ny * W + nx;
+          if (code[n] != O_A && code[n] != O_B) continue;
+          if (req[n] == O_REQ_NONE) continue;
+          target_of(req[n], nx, ny, heading(code[n]), &tx, &ty);
+          if (tx != x || ty != y) continue;
+          {
+            uint32_t w[4];
+            uint32_t k = id[n] - 1u;
+            agent_words(p->seed, t, k, w);
+            if (!have || w[0] < best_ticket || (w[0] == best_ticket && k < best_k)) {
+              have = 1;
+              best_ticket = w[0];
+              best_k = k;
+              best_dx = dx;
+              best_dy = dy;
+            }
+          }
+        }
+      if (have) {
+        size_t n = (size_t)(y + best_dy) * W + (x + best_dx);
+        new_code[c] = code[n];
+        new_id[c] = id[n];
+        new_code[n] = O_EMPTY;
+        new_id[n] = 0;
+        moved += 1;
+        if (win_out) win_out[c] = (uint8_t)(1 + (best_dy + 1) * 3 + (best_dx + 1));
+      }
+    }
+  if (req_out) memcpy(req_out, req, cells);
+  memcpy(code, new_code, cells);
+  memcpy(id, new_id, cells * sizeof(uint32_t));
+
+  /* 4. pheromone: evaporation (eq. 3) then deposit (eq. 4), both planes */
+  if (mode == 1) {
+    float rho = p->rho;
+    float keep = 1.0f - rho;
+    size_t c;
+    for (c = 0; c < cells; ++c) {
+      float va = keep * tau_a[c];
+      float vb = keep * tau_b[c];
+      if (code[c] == O_A) va = va + p->dtau;
+      if (code[c] == O_B) vb = vb + p->dtau;
+      tau_a[c] = va;
+      tau_b[c] = vb;
+    }
+  }
+  free(req);
+  free(new_code);
+  free(new_id);
+  return moved;
+}
+
+/* Crossing and population counts of the current state:
+ * out[0] agents in A, out[1] agents in B, out[2] A at x >= W - cross_b,
+ * out[3] B at x < cross_a. */
+void oracle_counts(const oracle_params *p, const uint8_t *code, uint64_t out[4]) {
+  int x, y;
+  memset(out, 0, 4 * sizeof(uint64_t));
+  for (y = 0; y < p->H; ++y)
+    for (x = 0; x < p->W; ++x) {
+      int g = code[(size_t)y * p->W + x];
+      if (g == O_A) {
+        out[0] += 1;
+        if (x >= p->W - p->cross_b) out[2] += 1;
+      } else if (g == O_B) {
+        out[1] += 1;
+        if (x < p->cross_a) out[3] += 1;
+      }
+    }
+}
+
+/* nsteps steps from step t0; returns the moves of the last step (or -1). */
+int64_t oracle_run(const oracle_params *p, int32_t mode, uint64_t t0, int64_t nsteps,
+                   uint8_t *code, uint32_t *id, float *tau_a, float *tau_b) {
+  int64_t s, moved = 0;
+  for (s = 0; s < nsteps; ++s) {
+    moved = oracle_step(p, mode, t0 + (uint64_t)s, code, id, tau_a, tau_b, NULL, NULL);
+    if (moved < 0) return -1;
+  }
+  return moved;
+}

@@ -1,0 +1,156 @@
+"""Second, pure-Python implementation of the oracle's step for tiny grids.
+
+TEST INFRASTRUCTURE ONLY. It is written independently of pedsim_oracle.c
+(scatter from the requesters instead of gathering at the cells, big-int
+Philox, numpy float32 scalars for every float operation) so that an indexing
+or ordering slip in either one shows up as a disagreement. Same readings of
+the paper as the C oracle (request per Sec. III / IV.b-c with eq. 1 or eq. 2,
+scatter-to-gather resolve per Sec. IV.d, evaporation eq. 3 then deposit
+eq. 4).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+F32 = np.float32
+MASK = 0xFFFFFFFF
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 (Salmon et al., SC'11) on Python ints."""
+    x = [int(c) & MASK for c in ctr]
+    k = [int(v) & MASK for v in key]
+    for rnd in range(10):
+        if rnd:
+            k = [(k[0] + 0x9E3779B9) & MASK, (k[1] + 0xBB67AE85) & MASK]
+        a = 0xD2511F53 * x[0]
+        b = 0xCD9E8D57 * x[2]
+        x = [(b >> 32) ^ x[1] ^ k[0], b & MASK, (a >> 32) ^ x[3] ^ k[1], a & MASK]
+    return x
+
+
+def _phi(z):
+    return 0.5 * math.erfc(-z / math.sqrt(2.0))
+
+
+# ceil(2^32 * Phi(j + 1/2)); double precision is ample here because none of
+# the three products lies within 1e-6 of an integer.
+THRESHOLDS = [int(math.ceil(4294967296.0 * _phi(j + 0.5))) for j in range(3)]
+
+# candidate offsets (dx in units of the heading d, dy)
+CAND = {1: (1, 0), 2: (1, -1), 3: (1, 1), 4: (0, -1), 5: (0, 1)}
+
+
+def _weight(d2, beta):
+    return F32(float(d2) ** (-0.5 * beta))
+
+
+def step(code, ids, tau, *, mode, t, seed, rho, dtau, alpha, beta):
+    """One step on copies; returns (code, ids, tau, req, moved)."""
+    H, W = code.shape
+    code = code.copy()
+    ids = ids.copy()
+    tau = None if tau is None else tau.copy()
+    key = (seed & MASK, seed >> 32)
+
+    def words(k):
+        return philox4x32_10((k, t & MASK, t >> 32, 0), key)
+
+    def empty(x, y):
+        return 0 <= x < W and 0 <= y < H and code[y, x] == 0
+
+    def lem(avail, r1, r2):
+        order = [3, 2, 5, 4] if (r2 & 1) else [2, 3, 4, 5]
+        ranked = [r for r in order if avail[r]]
+        if not ranked:
+            return 0
+        idx = sum(1 for th in THRESHOLDS if r1 >= th)
+        return ranked[min(idx, len(ranked) - 1)]
+
+    req = np.zeros((H, W), dtype=np.uint8)
+    for y in range(H):
+        for x in range(W):
+            g = int(code[y, x])
+            if g not in (1, 2):
+                continue
+            d = 1 if g == 1 else -1
+            if empty(x + d, y):
+                req[y, x] = 1
+                continue
+            avail = {}
+            for r in (2, 3, 4, 5):
+                ox, oy = CAND[r]
+                avail[r] = empty(x + ox * d, y + oy)
+            if not any(avail.values()):
+                continue
+            w = words(int(ids[y, x]) - 1)
+            if mode == 0:
+                req[y, x] = lem(avail, w[1], w[2])
+                continue
+            plane = tau[g - 1]
+            ws = []
+            for r in (2, 3, 4, 5):
+                if not avail[r]:
+                    ws.append(F32(0.0))
+                    continue
+                ox, oy = CAND[r]
+                tv = F32(plane[y + oy, x + ox * d])
+                p = F32(1.0)
+                if alpha > 0:
+                    p = tv
+                    for _ in range(alpha - 1):
+                        p = F32(p * tv)
+                ws.append(F32(p * _weight(2 if r in (2, 3) else 5, beta)))
+            s = F32(F32(F32(ws[0] + ws[1]) + ws[2]) + ws[3])
+            if s == F32(0.0):
+                req[y, x] = lem(avail, w[1], w[2])
+                continue
+            u = F32(F32(w[1] >> 8) * F32(2.0 ** -24))
+            target = F32(u * s)
+            run = F32(0.0)
+            pick = None
+            last = None
+            for i, r in enumerate((2, 3, 4, 5)):
+                run = F32(run + ws[i])
+                if ws[i] > 0:
+                    last = r
+                    if target < run:
+                        pick = r
+                        break
+            req[y, x] = pick if pick is not None else last
+
+    # scatter: every requester registers at its target; lowest (ticket, k) kept
+    best = {}
+    for y in range(H):
+        for x in range(W):
+            r = int(req[y, x])
+            if r == 0:
+                continue
+            g = int(code[y, x])
+            d = 1 if g == 1 else -1
+            ox, oy = CAND[r]
+            tx, ty = x + ox * d, y + oy
+            k = int(ids[y, x]) - 1
+            cand = (words(k)[0], k, x, y)
+            if (tx, ty) not in best or cand[:2] < best[(tx, ty)][:2]:
+                best[(tx, ty)] = cand
+    new_code = code.copy()
+    new_ids = ids.copy()
+    for (tx, ty), (_, _, sx, sy) in best.items():
+        new_code[ty, tx] = code[sy, sx]
+        new_ids[ty, tx] = ids[sy, sx]
+        new_code[sy, sx] = 0
+        new_ids[sy, sx] = 0
+    if mode == 1:
+        keep = F32(F32(1.0) - F32(rho))
+        for g in (1, 2):
+            plane = tau[g - 1]
+            for y in range(H):
+                for x in range(W):
+                    v = F32(keep * plane[y, x])
+                    if new_code[y, x] == g:
+                        v = F32(v + F32(dtau))
+                    plane[y, x] = v
+    return new_code, new_ids, tau, req, len(best)
