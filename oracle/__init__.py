@@ -17,6 +17,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pedsim_oracle.c")
 _LIB = os.path.join(_HERE, "libpedsim_oracle.so")
+# The mutation tests point this at a deliberately broken build of the oracle.
+_LIB_OVERRIDE = os.environ.get("PEDSIM_ORACLE_LIB")
 
 MODE_LEM, MODE_ACO = 0, 1
 
@@ -46,9 +48,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = _LIB_OVERRIDE or _LIB
+        if not _LIB_OVERRIDE and not os.path.exists(_LIB):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path)
         P = ctypes.POINTER
         L.oracle_philox4x32_10.argtypes = [P(ctypes.c_uint32), P(ctypes.c_uint32),
                                            P(ctypes.c_uint32)]

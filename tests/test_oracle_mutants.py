@@ -1,0 +1,58 @@
+"""Planted mistakes in the oracle must fail its pins.
+
+Each mutant is a copy of pedsim_oracle.c with one plausible slip (a swapped
+operand, a wrong sign, a dropped term, a reversed comparison), compiled on
+the CPU into a temporary library; the pin suite is then run against it and
+must fail. This shows the pins constrain every part of the oracle.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "pedsim_oracle.c")
+
+MUTANTS = {
+    "philox_high_halves_swapped": ("x0 = hi1 ^ x1 ^ k0;", "x0 = hi0 ^ x1 ^ k0;"),
+    "philox_key_bumped_before_first_round": ("if (round > 0) {", "if (round >= 0) {"),
+    "lem_side_order_ignored": ("(r2 & 1u) ? plus_first : minus_first",
+                               "(r2 & 0u) ? plus_first : minus_first"),
+    "lem_threshold_index_dropped": ("if (r1 >= lem_threshold[i]) index += 1;",
+                                    "if (r1 >= lem_threshold[0]) index += 1;"),
+    "aco_weights_swapped": ("(i < 2 ? eta_diag : eta_lat)", "(i < 2 ? eta_lat : eta_diag)"),
+    "aco_uses_r2": ("u = (float)(r1 >> 8) * 0x1p-24f;", "u = (float)(r2 >> 8) * 0x1p-24f;"),
+    "aco_alpha_ignored": ("for (a = 1; a < alpha; ++a)", "for (a = 1; a < 1; ++a)"),
+    "deposit_before_evaporation": ("float va = keep * tau_a[c];",
+                                   "float va = keep * (tau_a[c] + (code[c] == O_A ? p->dtau : 0.0f));"),
+    "winner_highest_ticket": ("w[0] < best_ticket ||", "w[0] > best_ticket ||"),
+    "source_id_not_cleared": ("new_id[n] = 0;", "(void)0;"),
+    "diagonal_sign_flipped": ("case O_REQ_FDP: *tx = x + d; *ty = y + 1; break;",
+                              "case O_REQ_FDP: *tx = x + d; *ty = y - 1; break;"),
+    "b_heads_plus_x": ("return group == O_A ? 1 : -1;", "return 1;"),
+    "forward_first_dropped": ("if (free_cell(p, code, x + d, y)) return O_REQ_F;", ""),
+    "other_groups_pheromone": ("(g == O_A) ? tau_a : tau_b", "(g == O_A) ? tau_b : tau_a"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_fails_a_pin(name):
+    old, new = MUTANTS[name]
+    with open(SRC) as f:
+        src = f.read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+    with tempfile.TemporaryDirectory() as d:
+        msrc = os.path.join(d, "mutant.c")
+        mlib = os.path.join(d, "libmutant.so")
+        with open(msrc, "w") as f:
+            f.write(src.replace(old, new))
+        subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
+                        "-o", mlib, msrc, "-lm"], check=True)
+        env = dict(os.environ, PEDSIM_ORACLE_LIB=mlib)
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                            os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+        assert r.returncode != 0, f"mutant {name} passed every pin"
