@@ -1,0 +1,183 @@
+"""Benchmark: agent-steps/s of the ACO step at 100K agents on one MI355X.
+
+A step is one pass of the whole hot path (request, resolve, commit,
+evaporation + deposit, counters) over the 1024x512 grid with 50,000 agents
+per group (seeded synthetic input, inputs resident in HBM before timing).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+WORKLOADS = {
+    "aco_1024x512": ("aco_1024x512", "ACO 1024x512, 50,000 agents per group (100K), 2,000 steps"),
+    "lem_200x100": ("lem_200x100", "LEM 200x100, 1,000 agents per group, 500 steps"),
+    "stress_aco_4096x2048": ("stress_4096x2048", "ACO 4096x2048, 5% obstacles, 1M agents"),
+    "stress_lem_4096x2048": ("stress_4096x2048", "LEM 4096x2048, 5% obstacles, 1M agents"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make(workload):
+    from paper_1412_4933_amd import scenarios as S
+    if workload == "stress_lem_4096x2048":
+        return S.stress_4096x2048(S.MODE_LEM)
+    return getattr(S, WORKLOADS[workload][0])()
+
+
+def algorithmic_bytes(kernel: str, mode: int, cells: int, agents: int) -> int:
+    """Bytes the method itself must move per launch (lower bound, mover
+    updates left out): decide reads every code byte and every agent's id;
+    commit reads every code byte and, for ACO, reads and writes both
+    pheromone planes (8 B read + 8 B write per cell)."""
+    if kernel == "decide":
+        return cells * 1 + agents * 4
+    if kernel == "commit":
+        return cells * (1 + (16 if mode == 1 else 0))
+    return cells * (17 if mode == 1 else 1) + agents * 4
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1412_4933_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, only
+    if they were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_src_digest") != kernel_source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(workload: str, budget_s: float):
+    import oracle
+    scn = make(workload)
+    st = oracle.State.from_scenario(scn)
+    # size the sample to roughly budget_s of single-thread work
+    t0 = time.perf_counter()
+    st.run(scn.mode, 5)
+    per = (time.perf_counter() - t0) / 5
+    n = max(5, min(scn.steps - 5, int(budget_s / max(per, 1e-6))))
+    t0 = time.perf_counter()
+    st.run(scn.mode, n)
+    dt = time.perf_counter() - t0
+    return {"value": scn.agents * n / dt, "unit": "agent-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"steps 5..{5 + n} of the {WORKLOADS[workload][1]} workload, "
+                      f"plain C oracle, one thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="aco_1024x512", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1412_4933_amd import pedsim
+
+    scn = make(args.workload)
+    mode = scn.mode if args.workload != "stress_aco_4096x2048" else 1
+    K = args.steps if args.steps is not None else scn.steps
+    cells, agents = scn.W * scn.H, scn.agents
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(dev)
+
+    # warmup on a throwaway copy, then time K steps from the initial state
+    log(f"workload {args.workload}: {scn.W}x{scn.H}, {agents} agents, mode {mode}, K={K}")
+    if args.warmup > 0:
+        w = pedsim.Sim(scn, stream=stream)
+        w.step(args.warmup, mode)
+        w.stats()
+        w.close()
+    sim = pedsim.Sim(scn, stream=stream)
+    torch.cuda.synchronize(dev)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    sim.step(K, mode)
+    end.record(stream)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(end)
+    stats = sim.stats()
+    sim.close()
+    sec = ms / 1e3
+    value = agents * K / sec
+    log(f"timed {K} steps: {ms:.3f} ms (wall {wall * 1e3:.3f} ms), stats {stats}")
+
+    # per-kernel durations with HIP events on the launch stream
+    prof = pedsim.Sim(scn, stream=stream)
+    per_kernel = pedsim.sim_step_timed(prof.h, mode, K, stream)
+    prof.close()
+    log("per-kernel:", {k: (round(v[0], 3), v[1]) for k, v in per_kernel.items()})
+    dom = max(per_kernel, key=lambda k: per_kernel[k][0])
+    dom_ms, dom_n = per_kernel[dom]
+    avg_s = dom_ms / dom_n / 1e3
+    alg = algorithmic_bytes(dom, mode, cells, agents)
+    achieved = alg / avg_s / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(args.workload, dom),
+                "avg_launch_us": round(avg_s * 1e6, 3), "alg_bytes_per_launch": alg,
+                "kernels": {k: {"avg_us": round(v[0] / v[1] * 1e3, 3), "launches": v[1]}
+                            for k, v in per_kernel.items()}}
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle ...")
+        cpu = cpu_baseline(args.workload, args.cpu_budget)
+        log(f"cpu oracle: {cpu['value']:.4g} agent-steps/s")
+
+    line = {
+        "metric": "agent-steps/s (ACO, 100K agents)" if args.workload == "aco_1024x512"
+        else f"agent-steps/s ({args.workload})",
+        "value": value, "unit": "agent-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": ms / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+u32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload][1], "grid": f"{scn.W}x{scn.H}",
+                   "agents": agents, "mode": "ACO" if mode == 1 else "LEM", "seed": scn.seed},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

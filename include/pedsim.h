@@ -1,0 +1,151 @@
+/*
+ * pedsim: the per-time-step bi-directional pedestrian update of Dutta, McLeod
+ * and Friesen (arXiv 1412.4933) on one MI355X (gfx950), as a C ABI.
+ *
+ * Two groups walk toward opposite sides of a 2D grid (Sec. III). Each step
+ * (Sec. IV.b-d):
+ *   request   every agent picks a target: the forward cell if it is empty,
+ *             otherwise one empty forward-diagonal or lateral cell chosen by
+ *             the Least Effort Model (eq. 1) or by the ACO random-proportional
+ *             rule on its group's pheromone (eq. 2);
+ *   resolve   every empty cell gathers the neighbours that picked it and
+ *             keeps one (scatter-to-gather, Sec. IV.d);
+ *   commit    winners move, everybody else stays;
+ *   pheromone (ACO) both planes evaporate (eq. 3) and gain a deposit on the
+ *             cells their group occupies (eq. 4).
+ *
+ * Frame and encoding
+ *   Cell (x, y), x = column 0..W-1, y = row 0..H-1, flat index y*W + x
+ *   (row-major, pitch W). Planes:
+ *     code  uint8  [H*W]   0 empty, 1 group A (heads +x), 2 group B (heads -x),
+ *                          3 wall. Outside the grid counts as wall.
+ *     id    uint32 [H*W]   agent number + 1 on cells with code 1 or 2, else 0.
+ *                          The agents' ids must be exactly 1..N.
+ *     tau   float  [2*H*W] pheromone, plane 0 for group A then plane 1 for B
+ *                          (only needed for ACO steps; may be NULL).
+ *   Candidates of an agent at (x, y) heading d: F (x+d, y), FD- (x+d, y-1),
+ *   FD+ (x+d, y+1), L- (x, y-1), L+ (x, y+1); staying is implicit.
+ *
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11) with counter
+ * (agent number, step low word, step high word, 0) and key (seed low word,
+ * seed high word), so results do not depend on thread order, tile shape or
+ * launch configuration. Conflicts go to the lowest (word 0, agent number).
+ * Pheromone arithmetic is IEEE binary32 with no fused multiply-add and with
+ * subnormals kept, so results are bit-identical to a plain sequential
+ * evaluation of the same rules.
+ *
+ * Ownership: the caller allocates every device buffer (planes and scratch)
+ * and keeps it alive while a handle uses it. The library allocates no device
+ * memory. A handle is not thread-safe; distinct handles are independent.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ * stream). Step calls are asynchronous and stream-ordered; once the stream
+ * has reached the end of a call, the caller's planes hold the state after
+ * its last step.
+ *
+ * Errors: every call returns SIM_OK (0) or a negative SIM_E* code; nothing
+ * is thrown or aborted across the ABI. sim_strerror() names a code.
+ */
+#ifndef PEDSIM_H
+#define PEDSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIM_OK 0
+#define SIM_EINVAL (-1)   /* bad argument or parameter */
+#define SIM_ESTATE (-2)   /* initial planes are not a valid state */
+#define SIM_ESCRATCH (-3) /* scratch buffer missing or too small */
+#define SIM_EHIP (-4)     /* a HIP runtime call failed */
+#define SIM_ENOTAU (-5)   /* ACO step on a handle created without pheromone */
+#define SIM_EFULL (-6)    /* batch has no free slot */
+
+#define SIM_MODE_LEM 0
+#define SIM_MODE_ACO 1
+
+typedef struct sim_handle sim_handle;
+
+/* Parameters of one scenario. */
+typedef struct {
+  int32_t W, H;      /* grid columns and rows, 1 <= W, H; W*H < 2^31 */
+  uint64_t seed;     /* Philox key */
+  uint64_t step0;    /* index of the first step to run (0 for a fresh start;
+                        the saved step counter when resuming a checkpoint) */
+  float rho;         /* evaporation rate, 0 < rho <= 1 (eq. 3) */
+  float dtau;        /* deposit per occupied cell per step, finite, >= 0 (eq. 4) */
+  int32_t alpha;     /* pheromone exponent of eq. 2, 0..8 */
+  int32_t beta;      /* heuristic exponent of eq. 2, 0..8 */
+  int32_t cross_a;   /* B has crossed once x <  cross_a, 0..W */
+  int32_t cross_b;   /* A has crossed once x >= W - cross_b, 0..W */
+} sim_params;
+
+/* Counters of a scenario after its last completed step. */
+typedef struct {
+  uint64_t step;       /* steps run so far, counting step0 */
+  uint64_t agents_a;   /* agents of group A (constant) */
+  uint64_t agents_b;   /* agents of group B (constant) */
+  uint64_t crossed_a;  /* A agents with x >= W - cross_b (throughput, Sec. VI) */
+  uint64_t crossed_b;  /* B agents with x <  cross_a */
+  uint64_t moved_last; /* agents that moved in the last step */
+} sim_stats_t;
+
+/* Bytes of device scratch a scenario with these parameters needs
+ * (1 byte per cell plus small per-tile counters). */
+int sim_scratch_bytes(const sim_params* p, size_t* out);
+
+/*
+ * Create a handle over caller-owned device planes that hold the initial
+ * state (layout above) and a device scratch buffer of at least
+ * sim_scratch_bytes(). d_tau may be NULL (then only LEM steps are allowed).
+ * The planes are validated on the device: codes in 0..3, ids consistent with
+ * codes and exactly 1..N, pheromone finite and >= 0; a bad state returns
+ * SIM_ESTATE. Synchronises `stream`.
+ */
+int sim_create(const sim_params* p, uint8_t* d_code, uint32_t* d_id, float* d_tau,
+               void* d_scratch, size_t scratch_bytes, void* stream, sim_handle** out);
+
+/* Run nsteps (>= 0) Least Effort Model steps (eq. 1), asynchronously. */
+int sim_step_lem(sim_handle* h, int32_t nsteps, void* stream);
+
+/* Run nsteps (>= 0) ACO steps (eq. 2 choice, eq. 3 and 4 update),
+ * asynchronously; SIM_ENOTAU if the handle has no pheromone planes. */
+int sim_step_aco(sim_handle* h, int32_t nsteps, void* stream);
+
+/* Counters after the last completed step; synchronises `stream`. */
+int sim_stats(sim_handle* h, sim_stats_t* out, void* stream);
+
+/* Copy the current state (a checkpoint, with the step counter from
+ * sim_stats) into caller buffers, device or host: code [H*W], id [H*W],
+ * tau [2*H*W] (ignored when NULL or when the handle has no pheromone).
+ * Synchronises `stream`. */
+int sim_read_state(sim_handle* h, uint8_t* code, uint32_t* id, float* tau, void* stream);
+
+/*
+ * Instrumentation: run nsteps steps of `mode` (SIM_MODE_LEM or SIM_MODE_ACO)
+ * exactly as sim_step_* does, but bracket every kernel launch with HIP events
+ * recorded on `stream`, and add each kernel kind's elapsed milliseconds into
+ * kernel_ms[kind] and its launch count into launches[kind] (arrays of
+ * max_kinds entries, not cleared). Kind names come from sim_kernel_name().
+ * Returns the number of kernel kinds (>= 0) or a SIM_E* code. Synchronises.
+ */
+int sim_step_timed(sim_handle* h, int32_t mode, int32_t nsteps, void* stream, double* kernel_ms,
+                   int64_t* launches, int32_t max_kinds);
+
+/* Static name of kernel kind `kind` reported by sim_step_timed ("" if none). */
+const char* sim_kernel_name(int32_t kind);
+
+/* Release a handle (not the caller's buffers). NULL is ignored. */
+void sim_destroy(sim_handle* h);
+
+/* Static text for a SIM_* code. */
+const char* sim_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PEDSIM_H */

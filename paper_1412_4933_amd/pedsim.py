@@ -1,0 +1,239 @@
+"""Python binding of the pedsim C ABI (include/pedsim.h).
+
+Argument marshalling only: every step runs in the HIP kernels of
+libpedsim.so. PyTorch provides device memory (tensors) and streams. The
+library must have been built (`python -m paper_1412_4933_amd.build` or
+`__graft_entry__.build()`); if it is missing, loading fails loudly rather than
+falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpedsim.so")
+
+SIM_OK, SIM_EINVAL, SIM_ESTATE, SIM_ESCRATCH, SIM_EHIP, SIM_ENOTAU, SIM_EFULL = 0, -1, -2, -3, -4, -5, -6
+SIM_MODE_LEM, SIM_MODE_ACO = 0, 1
+
+
+class SimError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {sim_strerror(code)} ({code})")
+
+
+class SimParams(ctypes.Structure):
+    _fields_ = [
+        ("W", ctypes.c_int32), ("H", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("step0", ctypes.c_uint64),
+        ("rho", ctypes.c_float), ("dtau", ctypes.c_float),
+        ("alpha", ctypes.c_int32), ("beta", ctypes.c_int32),
+        ("cross_a", ctypes.c_int32), ("cross_b", ctypes.c_int32),
+    ]
+
+
+class SimStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in
+                ("step", "agents_a", "agents_b", "crossed_a", "crossed_b", "moved_last")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+        P = ctypes.POINTER
+        L.sim_strerror.argtypes = [ctypes.c_int]
+        L.sim_strerror.restype = ctypes.c_char_p
+        L.sim_scratch_bytes.argtypes = [P(SimParams), P(sz)]
+        L.sim_create.argtypes = [P(SimParams), vp, vp, vp, vp, sz, vp, P(vp)]
+        L.sim_step_lem.argtypes = [vp, i32, vp]
+        L.sim_step_aco.argtypes = [vp, i32, vp]
+        L.sim_stats.argtypes = [vp, P(SimStats), vp]
+        L.sim_read_state.argtypes = [vp, vp, vp, vp, vp]
+        L.sim_step_timed.argtypes = [vp, i32, i32, vp, P(ctypes.c_double), P(ctypes.c_int64), i32]
+        L.sim_step_timed.restype = ctypes.c_int
+        L.sim_kernel_name.argtypes = [i32]
+        L.sim_kernel_name.restype = ctypes.c_char_p
+        L.sim_destroy.argtypes = [vp]
+        L.sim_destroy.restype = None
+        for name in ("sim_scratch_bytes", "sim_create", "sim_step_lem", "sim_step_aco",
+                     "sim_stats", "sim_read_state"):
+            getattr(L, name).restype = ctypes.c_int
+        _bind_batch(L)
+        _lib = L
+    return _lib
+
+
+def _bind_batch(L):
+    if not hasattr(L, "sim_batch_create"):
+        return
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    P = ctypes.POINTER
+    L.sim_batch_create.argtypes = [i32, P(vp)]
+    L.sim_batch_add.argtypes = [vp, P(SimParams), i32, vp, vp, vp, vp, sz, vp, P(i32)]
+    L.sim_batch_remove.argtypes = [vp, i32]
+    L.sim_batch_step.argtypes = [vp, i32, vp]
+    L.sim_batch_step_slots.argtypes = [vp, P(i32), i32, vp]
+    L.sim_batch_stats.argtypes = [vp, i32, P(SimStats), vp]
+    L.sim_batch_destroy.argtypes = [vp]
+    L.sim_batch_destroy.restype = None
+    L.sim_batch_set_tuning.argtypes = [vp, i32, i32]
+    for name in ("sim_batch_create", "sim_batch_add", "sim_batch_remove", "sim_batch_step",
+                 "sim_batch_step_slots", "sim_batch_stats", "sim_batch_set_tuning"):
+        getattr(L, name).restype = ctypes.c_int
+
+
+def _check(code: int, what: str) -> None:
+    if code != SIM_OK:
+        raise SimError(code, what)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# --- the C ABI, name for name -------------------------------------------------
+
+def sim_strerror(code: int) -> str:
+    return lib().sim_strerror(int(code)).decode()
+
+
+def sim_scratch_bytes(params: SimParams) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().sim_scratch_bytes(ctypes.byref(params), ctypes.byref(out)), "sim_scratch_bytes")
+    return int(out.value)
+
+
+def sim_create(params: SimParams, code, ids, tau, scratch, scratch_bytes: int, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().sim_create(ctypes.byref(params), _ptr(code), _ptr(ids), _ptr(tau), _ptr(scratch),
+                            int(scratch_bytes), _stream(stream), ctypes.byref(h)), "sim_create")
+    return h
+
+
+def sim_step_lem(h, nsteps: int, stream=None) -> None:
+    _check(lib().sim_step_lem(h, int(nsteps), _stream(stream)), "sim_step_lem")
+
+
+def sim_step_aco(h, nsteps: int, stream=None) -> None:
+    _check(lib().sim_step_aco(h, int(nsteps), _stream(stream)), "sim_step_aco")
+
+
+def sim_stats(h, stream=None) -> dict:
+    s = SimStats()
+    _check(lib().sim_stats(h, ctypes.byref(s), _stream(stream)), "sim_stats")
+    return s.as_dict()
+
+
+def sim_read_state(h, code, ids, tau, stream=None) -> None:
+    _check(lib().sim_read_state(h, _ptr(code), _ptr(ids), _ptr(tau), _stream(stream)),
+           "sim_read_state")
+
+
+def sim_step_timed(h, mode: int, nsteps: int, stream=None) -> dict:
+    """Per-kernel-kind {name: (total_ms, launches)} over nsteps timed steps."""
+    n = 8
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    rc = lib().sim_step_timed(h, int(mode), int(nsteps), _stream(stream), ms, cnt, n)
+    if rc < 0:
+        raise SimError(rc, "sim_step_timed")
+    return {lib().sim_kernel_name(k).decode(): (float(ms[k]), int(cnt[k])) for k in range(rc)}
+
+
+def sim_kernel_name(kind: int) -> str:
+    return lib().sim_kernel_name(int(kind)).decode()
+
+
+def sim_destroy(h) -> None:
+    if h:
+        lib().sim_destroy(h)
+
+
+# --- convenience: a scenario resident in torch device tensors -------------------
+
+def params_of(s, step0: int = 0) -> SimParams:
+    """SimParams of a `scenarios.Scenario`."""
+    return SimParams(s.W, s.H, s.seed, step0, s.rho, s.dtau, s.alpha, s.beta, s.cross_a,
+                     s.cross_b)
+
+
+class Sim:
+    """One scenario resident on the GPU: device planes allocated with torch,
+    stepped by the library."""
+
+    def __init__(self, scenario, device: str = "cuda", stream=None, step0: int = 0):
+        import torch
+        self.torch = torch
+        self.scenario = scenario
+        self.device = torch.device(device)
+        self.stream = stream
+        self.params = params_of(scenario, step0)
+        self.code = torch.from_numpy(np.ascontiguousarray(scenario.code)).to(self.device)
+        self.ids = torch.from_numpy(np.ascontiguousarray(scenario.ids).view(np.int32)).to(self.device)
+        self.tau = None
+        if scenario.tau is not None:
+            self.tau = torch.from_numpy(np.ascontiguousarray(scenario.tau)).to(self.device)
+        nbytes = sim_scratch_bytes(self.params)
+        self.scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        self.h = sim_create(self.params, self.code, self.ids, self.tau, self.scratch, nbytes,
+                            stream)
+
+    def step(self, nsteps: int, mode: Optional[int] = None) -> None:
+        mode = self.scenario.mode if mode is None else mode
+        if mode == SIM_MODE_LEM:
+            sim_step_lem(self.h, nsteps, self.stream)
+        else:
+            sim_step_aco(self.h, nsteps, self.stream)
+
+    def stats(self) -> dict:
+        return sim_stats(self.h, self.stream)
+
+    def state(self):
+        """(code, ids, tau) copied to host numpy arrays."""
+        H, W = self.scenario.H, self.scenario.W
+        code = np.empty((H, W), np.uint8)
+        ids = np.empty((H, W), np.uint32)
+        tau = np.empty((2, H, W), np.float32) if self.tau is not None else None
+        sim_read_state(self.h, code.ctypes.data, ids.ctypes.data,
+                       None if tau is None else tau.ctypes.data, self.stream)
+        return code, ids, tau
+
+    def close(self) -> None:
+        if self.h:
+            sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

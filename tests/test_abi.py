@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1412_4933_amd import pedsim, scenarios
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pedsim.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sim_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("sim_create", "sim_step_lem", "sim_step_aco", "sim_stats", "sim_scratch_bytes",
+              "sim_read_state", "sim_destroy", "sim_strerror"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = pedsim.lib()
+    for n in declared_functions():
+        assert hasattr(L, n), n
+
+
+def test_strerror_names_every_code():
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert pedsim.sim_strerror(code) not in ("", "unknown error")
+    assert pedsim.sim_strerror(-99) == "unknown error"
+
+
+def _params(**kw):
+    base = dict(W=64, H=32, seed=1, step0=0, rho=0.1, dtau=1.0, alpha=1, beta=2, cross_a=4,
+                cross_b=4)
+    base.update(kw)
+    return pedsim.SimParams(**base)
+
+
+def test_scratch_bytes_cover_one_byte_per_cell():
+    for W, H in ((1, 1), (64, 32), (200, 100), (1024, 512), (4096, 2048), (777, 3)):
+        n = pedsim.sim_scratch_bytes(_params(W=W, H=H, cross_a=0, cross_b=0))
+        assert n >= W * H and n % 256 == 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(W=0), dict(H=0), dict(W=-3), dict(W=65536, H=32768), dict(rho=0.0), dict(rho=1.5),
+    dict(rho=float("nan")), dict(dtau=-1.0), dict(dtau=float("inf")), dict(alpha=-1),
+    dict(alpha=9), dict(beta=9), dict(cross_a=65), dict(cross_b=-1)])
+def test_bad_parameters_rejected_on_host(bad):
+    p = _params(**bad)
+    with pytest.raises(pedsim.SimError) as e:
+        pedsim.sim_scratch_bytes(p)
+    assert e.value.code == pedsim.SIM_EINVAL
+    h = ctypes.c_void_p()
+    rc = pedsim.lib().sim_create(ctypes.byref(p), 16, 16, None, 16, 1 << 20, None, ctypes.byref(h))
+    assert rc == pedsim.SIM_EINVAL and not h.value
+
+
+def test_missing_buffers_and_small_scratch_rejected_on_host():
+    p = _params()
+    need = pedsim.sim_scratch_bytes(p)
+    h = ctypes.c_void_p()
+    L = pedsim.lib()
+    assert L.sim_create(ctypes.byref(p), None, 16, None, 16, need, None, ctypes.byref(h)) == pedsim.SIM_EINVAL
+    assert L.sim_create(ctypes.byref(p), 16, 16, None, None, need, None, ctypes.byref(h)) == pedsim.SIM_ESCRATCH
+    assert L.sim_create(ctypes.byref(p), 16, 16, None, 16, need - 1, None, ctypes.byref(h)) == pedsim.SIM_ESCRATCH
+    assert L.sim_step_lem(None, 1, None) == pedsim.SIM_EINVAL
+    assert L.sim_step_aco(None, 1, None) == pedsim.SIM_EINVAL
+
+
+def test_params_of_scenario():
+    s = scenarios.lem_200x100()
+    p = pedsim.params_of(s)
+    assert (p.W, p.H, p.seed, p.cross_a, p.cross_b) == (200, 100, 1, 11, 11)
+    assert s.band_a == 11 and s.n_a == 1000
+
+
+def test_scenario_bands_follow_the_band_rule():
+    s = scenarios.aco_1024x512()
+    assert s.band_a == 99 and s.band_b == 99 and s.agents == 100000
+    import numpy as np
+    assert np.all(s.code[:, 99:1024 - 99] != scenarios.GROUP_A)
+    assert np.count_nonzero(s.code == scenarios.GROUP_A) == 50000
+    assert sorted(s.ids[s.ids != 0].tolist()) == list(range(1, 100001))
