@@ -41,16 +41,12 @@ def make(workload):
     return getattr(S, WORKLOADS[workload][0])()
 
 
-def algorithmic_bytes(kernel: str, mode: int, cells: int, agents: int) -> int:
-    """Bytes the method itself must move per launch (lower bound, mover
-    updates left out): decide reads every code byte and every agent's id;
-    commit reads every code byte and, for ACO, reads and writes both
-    pheromone planes (8 B read + 8 B write per cell)."""
-    if kernel == "decide":
-        return cells * 1 + agents * 4
-    if kernel == "commit":
-        return cells * (1 + (16 if mode == 1 else 0))
-    return cells * (17 if mode == 1 else 1) + agents * 4
+def algorithmic_bytes_per_step(mode: int, cells: int, agents: int) -> int:
+    """Bytes one step of the method must move (lower bound; the few bytes of
+    the agents that actually move are left out): every code byte is read,
+    every agent's id is read, and for ACO both pheromone planes are read and
+    written (8 B read + 8 B write per cell)."""
+    return cells * (1 + (16 if mode == 1 else 0)) + agents * 4
 
 
 def kernel_source_digest() -> str:
@@ -141,22 +137,25 @@ def main():
     value = agents * K / sec
     log(f"timed {K} steps: {ms:.3f} ms (wall {wall * 1e3:.3f} ms), stats {stats}")
 
-    # per-kernel durations with HIP events on the launch stream
+    # per-launch durations of the step kernel with HIP events on the launch stream
     prof = pedsim.Sim(scn, stream=stream)
+    tiling = pedsim.sim_get_tiling(prof.h, mode)
     per_kernel = pedsim.sim_step_timed(prof.h, mode, K, stream)
     prof.close()
+    log("tiling (nw, rows, steps/launch, threads):", tiling)
     log("per-kernel:", {k: (round(v[0], 3), v[1]) for k, v in per_kernel.items()})
-    dom = max(per_kernel, key=lambda k: per_kernel[k][0])
+    dom = "tile_kernel"
     dom_ms, dom_n = per_kernel[dom]
-    avg_s = dom_ms / dom_n / 1e3
-    alg = algorithmic_bytes(dom, mode, cells, agents)
-    achieved = alg / avg_s / 1e9
+    alg_step = algorithmic_bytes_per_step(mode, cells, agents)
+    achieved = alg_step * K / (dom_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(args.workload, dom),
-                "avg_launch_us": round(avg_s * 1e6, 3), "alg_bytes_per_launch": alg,
-                "kernels": {k: {"avg_us": round(v[0] / v[1] * 1e3, 3), "launches": v[1]}
-                            for k, v in per_kernel.items()}}
+                "avg_launch_us": round(dom_ms / dom_n * 1e3, 3),
+                "alg_bytes_per_launch": int(alg_step * K / dom_n),
+                "steps_per_launch": tiling[2],
+                "kernels": {k: {"avg_us": round(v[0] / v[1] * 1e3, 3) if v[1] else 0.0,
+                                "launches": v[1]} for k, v in per_kernel.items()}}
 
     cpu = None
     if not args.no_cpu:

@@ -125,12 +125,27 @@ int sim_stats(sim_handle* h, sim_stats_t* out, void* stream);
 int sim_read_state(sim_handle* h, uint8_t* code, uint32_t* id, float* tau, void* stream);
 
 /*
+ * Tiling of the step kernel for `mode` (results never depend on it): each
+ * workgroup of `threads` lanes (multiple of 64, <= 1024) stages a region of
+ * 64*nw columns (nw = 1 or 2) x `rows` rows (rows <= threads) in LDS and
+ * advances it `steps_per_launch` steps per launch; the tile interior is the
+ * region minus 3*steps_per_launch cells on every side and must be at least
+ * 16 x 8. SIM_EINVAL if the shape is not allowed or does not fit the LDS.
+ * sim_get_tiling writes {nw, rows, steps_per_launch, threads} into out[4].
+ */
+int sim_set_tiling(sim_handle* h, int32_t mode, int32_t nw, int32_t rows, int32_t steps_per_launch,
+                   int32_t threads);
+int sim_get_tiling(sim_handle* h, int32_t mode, int32_t out[4]);
+
+/*
  * Instrumentation: run nsteps steps of `mode` (SIM_MODE_LEM or SIM_MODE_ACO)
  * exactly as sim_step_* does, but bracket every kernel launch with HIP events
  * recorded on `stream`, and add each kernel kind's elapsed milliseconds into
  * kernel_ms[kind] and its launch count into launches[kind] (arrays of
- * max_kinds entries, not cleared). Kind names come from sim_kernel_name().
- * Returns the number of kernel kinds (>= 0) or a SIM_E* code. Synchronises.
+ * max_kinds >= 2 entries, not cleared): kind 0 is the step kernel, kind 1 the
+ * copy back into the caller's planes after an odd number of launches. Kind
+ * names come from sim_kernel_name(). Returns the number of kernel kinds or a
+ * SIM_E* code. Synchronises.
  */
 int sim_step_timed(sim_handle* h, int32_t mode, int32_t nsteps, void* stream, double* kernel_ms,
                    int64_t* launches, int32_t max_kinds);

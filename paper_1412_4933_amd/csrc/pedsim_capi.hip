@@ -1,4 +1,10 @@
 // C ABI of the single-scenario step (declared in include/pedsim.h).
+//
+// The state lives in the caller's planes between calls. Within a call the
+// tile engine ping-pongs between the caller's planes and a copy in the
+// scratch buffer (every launch reads one set and writes the other, because a
+// tile's halo is its neighbours' interior); the call ends with the state back
+// in the caller's planes.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -10,36 +16,35 @@
 
 using namespace pedsim;
 
-struct sim_handle {
-  sim_params p;
-  uint8_t* code;
-  uint32_t* id;
-  float* tau;  // 2*H*W or nullptr
-  StepArgs args;
-  unsigned long long* totals;  // kStatFields device totals (scratch)
-  int commit_blocks;
-  uint64_t t;  // index of the next step
-};
-
 namespace {
 
 constexpr size_t kAlign = 256;
-
 size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-struct Layout {
-  size_t dec, block_stats, totals, total;
-  int commit_bx, commit_by;
+struct Planes {
+  uint8_t* code;
+  uint32_t* id;
+  float* tau;
 };
 
-Layout layout_of(const sim_params* p) {
-  Layout L;
+struct ScratchLayout {
+  size_t code2, id2, tau2, stats, totals, total;
+  int stats_cap;
+};
+
+int count_entries(int W, int H) { return ((W + 63) / 64) * ((H + 3) / 4); }
+
+ScratchLayout layout_of(const sim_params* p) {
+  ScratchLayout L;
   const size_t cells = (size_t)p->W * (size_t)p->H;
-  L.commit_bx = (p->W + kCommitTX - 1) / kCommitTX;
-  L.commit_by = (p->H + kCommitTY - 1) / kCommitTY;
-  L.dec = 0;
-  L.block_stats = round_up(cells);
-  L.totals = L.block_stats + round_up((size_t)L.commit_bx * L.commit_by * kStatFields * sizeof(uint32_t));
+  const int max_tiles = ((p->W + kMinInteriorX - 1) / kMinInteriorX) * ((p->H + kMinInteriorY - 1) / kMinInteriorY);
+  const int ce = count_entries(p->W, p->H);
+  L.stats_cap = max_tiles > ce ? max_tiles : ce;
+  L.code2 = 0;
+  L.id2 = L.code2 + round_up(cells);
+  L.tau2 = L.id2 + round_up(cells * 4);
+  L.stats = L.tau2 + round_up(cells * 8);
+  L.totals = L.stats + round_up((size_t)L.stats_cap * kTileStatFields * 4);
   L.total = L.totals + round_up(8 * sizeof(unsigned long long));
   return L;
 }
@@ -48,7 +53,7 @@ int check_params(const sim_params* p) {
   if (!p) return SIM_EINVAL;
   if (p->W < 1 || p->H < 1) return SIM_EINVAL;
   if ((int64_t)p->W * (int64_t)p->H >= ((int64_t)1 << 31)) return SIM_EINVAL;
-  if ((p->H + kCommitTY - 1) / kCommitTY > 65535) return SIM_EINVAL;  // commit grid rows
+  if ((p->H + 3) / 4 > 65535) return SIM_EINVAL;  // count-kernel grid rows
   if (!(p->rho > 0.0f && p->rho <= 1.0f)) return SIM_EINVAL;
   if (!(p->dtau >= 0.0f && p->dtau <= 3.402823466e38f)) return SIM_EINVAL;
   if (p->alpha < 0 || p->alpha > 8 || p->beta < 0 || p->beta > 8) return SIM_EINVAL;
@@ -59,6 +64,132 @@ int check_params(const sim_params* p) {
 // eta^beta = D2^(-beta/2) for the squared distance D2 from a candidate to the
 // point two cells ahead (diagonal 2, lateral 5), rounded to float.
 float heuristic(double d2, int beta) { return (float)pow(d2, -0.5 * (double)beta); }
+
+// Default tiling by grid size (measured on MI355X): small grids want many
+// small tiles so every CU has one; large grids want tall regions and three
+// steps per launch. The first shape that fits the device's LDS is used.
+Tiling default_tiling(bool aco, size_t cells) {
+  static const Tiling small_opts[] = {{1, 32, 2, 512}, {1, 24, 2, 256}, {1, 32, 1, 256}};
+  static const Tiling large_opts[] = {{1, 128, 3, 1024}, {1, 64, 3, 512}, {1, 32, 1, 256}};
+  const Tiling* opts = cells < ((size_t)2 << 20) ? small_opts : large_opts;
+  for (int i = 0; i < 3; ++i)
+    if (tiling_valid(opts[i], aco, max_dynamic_lds())) return opts[i];
+  return opts[2];
+}
+
+}  // namespace
+
+struct sim_handle {
+  sim_params p;
+  Planes user;     // caller-owned state
+  Planes shadow;   // copy in scratch
+  uint32_t* stats;
+  int stats_cap;
+  int stats_entries;
+  unsigned long long* totals;
+  Scenario base;   // parameters shared by every launch
+  Tiling tiling[2];
+  uint64_t t;      // index of the next step
+};
+
+namespace {
+
+void set_geometry(Scenario& S, const Tiling& tl) {
+  S.halo = 3 * tl.steps;
+  S.IX = 64 * tl.nw - 2 * S.halo;
+  S.IY = tl.rows - 2 * S.halo;
+  S.tiles_x = (S.W + S.IX - 1) / S.IX;
+  S.tiles_y = (S.H + S.IY - 1) / S.IY;
+}
+
+hipError_t copy_planes(const Planes& dst, const Planes& src, size_t cells, bool tau, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(dst.code, src.code, cells, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst.id, src.id, cells * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && tau) e = hipMemcpyAsync(dst.tau, src.tau, cells * 8, hipMemcpyDeviceToDevice, s);
+  return e;
+}
+
+// Launch plan for n steps: chunks of at most tl.steps, with an even number of
+// launches when possible so the state ends in the caller's planes.
+int plan(int nsteps, int per, int* chunks, int cap) {
+  int n = 0;
+  for (int done = 0; done < nsteps && n < cap; ++n) {
+    chunks[n] = nsteps - done < per ? nsteps - done : per;
+    done += chunks[n];
+  }
+  if ((n & 1) && n < cap) {
+    for (int j = n - 1; j >= 0; --j)
+      if (chunks[j] >= 2) {
+        for (int m = n; m > j + 1; --m) chunks[m] = chunks[m - 1];
+        chunks[j + 1] = chunks[j] / 2;
+        chunks[j] -= chunks[j + 1];
+        ++n;
+        break;
+      }
+  }
+  return n;
+}
+
+// Run nsteps steps; ev (optional, 2 events) brackets each tile launch, and
+// its elapsed time is added into ms[0] (launches[0]); a copy-back is timed
+// into ms[1] (launches[1]).
+int run_steps(sim_handle* h, int mode, int32_t nsteps, hipStream_t s, hipEvent_t* ev, double* ms,
+              int64_t* launches) {
+  if (nsteps == 0) return SIM_OK;
+  const Tiling& tl = h->tiling[mode];
+  Scenario S = h->base;
+  set_geometry(S, tl);
+  const size_t cells = (size_t)S.W * (size_t)S.H;
+  const bool aco = mode == kModeAco;
+  Planes src = h->user, dst = h->shadow;
+  int chunk[64];
+  int done = 0;
+  while (done < nsteps) {
+    // plan at most 64 launches at a time (keeps the parity logic simple)
+    const int remain = nsteps - done;
+    const int span = remain < 62 * tl.steps ? remain : 62 * tl.steps;
+    const int n = plan(span, tl.steps, chunk, 64);
+    for (int j = 0; j < n; ++j) {
+      S.code_in = src.code;
+      S.id_in = src.id;
+      S.tau_in = aco ? src.tau : nullptr;
+      S.code_out = dst.code;
+      S.id_out = dst.id;
+      S.tau_out = aco ? dst.tau : nullptr;
+      S.tile_stats = h->stats;
+      const bool last = done + chunk[j] == nsteps;
+      if (ev) (void)hipEventRecord(ev[0], s);
+      if (launch_tiles(S, tl, mode, h->t, chunk[j], last, s) != hipSuccess) return SIM_EHIP;
+      if (ev) {
+        (void)hipEventRecord(ev[1], s);
+        if (hipEventSynchronize(ev[1]) != hipSuccess) return SIM_EHIP;
+        float f = 0.0f;
+        (void)hipEventElapsedTime(&f, ev[0], ev[1]);
+        ms[0] += f;
+        launches[0] += 1;
+      }
+      h->t += (uint64_t)chunk[j];
+      done += chunk[j];
+      const Planes tmp = src;
+      src = dst;
+      dst = tmp;
+    }
+  }
+  if (src.code != h->user.code) {  // odd number of launches: state is in the shadow planes
+    if (ev) (void)hipEventRecord(ev[0], s);
+    if (copy_planes(h->user, src, cells, aco, s) != hipSuccess) return SIM_EHIP;
+    if (ev) {
+      (void)hipEventRecord(ev[1], s);
+      if (hipEventSynchronize(ev[1]) != hipSuccess) return SIM_EHIP;
+      float f = 0.0f;
+      (void)hipEventElapsedTime(&f, ev[0], ev[1]);
+      ms[1] += f;
+      launches[1] += 1;
+    }
+  }
+  h->stats_entries = S.tiles_x * S.tiles_y;
+  return SIM_OK;
+}
 
 }  // namespace
 
@@ -91,13 +222,13 @@ int sim_create(const sim_params* p, uint8_t* d_code, uint32_t* d_id, float* d_ta
   if (e) return e;
   if (!d_code || !d_id || !out) return SIM_EINVAL;
   *out = nullptr;
-  const Layout L = layout_of(p);
+  const ScratchLayout L = layout_of(p);
   if (!d_scratch || scratch_bytes < L.total) return SIM_ESCRATCH;
   hipStream_t s = (hipStream_t)stream;
   uint8_t* scratch = (uint8_t*)d_scratch;
   const size_t cells = (size_t)p->W * (size_t)p->H;
   unsigned long long* totals = (unsigned long long*)(scratch + L.totals);
-  unsigned long long* counters = totals + kStatFields;  // 3 validation counters
+  unsigned long long* counters = totals + kTileStatFields;  // 3 validation counters
 
   // Validate the initial state on the device.
   unsigned long long host_counters[3];
@@ -109,7 +240,7 @@ int sim_create(const sim_params* p, uint8_t* d_code, uint32_t* d_id, float* d_ta
   if (host_counters[2]) return SIM_ESTATE;
   const unsigned long long n = host_counters[0] + host_counters[1];
   if (n > 0) {
-    uint32_t* bitmap = (uint32_t*)(scratch + L.dec);
+    uint32_t* bitmap = (uint32_t*)(scratch + L.id2);
     if (hipMemsetAsync(bitmap, 0, (n + 31) / 32 * sizeof(uint32_t), s) != hipSuccess) return SIM_EHIP;
     if (launch_validate_ids(d_id, cells, (uint32_t)n, bitmap, counters, s) != hipSuccess) return SIM_EHIP;
     if (hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -121,37 +252,29 @@ int sim_create(const sim_params* p, uint8_t* d_code, uint32_t* d_id, float* d_ta
   sim_handle* h = new (std::nothrow) sim_handle;
   if (!h) return SIM_EINVAL;
   h->p = *p;
-  h->code = d_code;
-  h->id = d_id;
-  h->tau = d_tau;
+  h->user = Planes{d_code, d_id, d_tau};
+  h->shadow = Planes{scratch + L.code2, (uint32_t*)(scratch + L.id2), d_tau ? (float*)(scratch + L.tau2) : nullptr};
+  h->stats = (uint32_t*)(scratch + L.stats);
+  h->stats_cap = L.stats_cap;
   h->totals = totals;
-  h->commit_blocks = L.commit_bx * L.commit_by;
   h->t = p->step0;
-  StepArgs& a = h->args;
-  a.code = d_code;
-  a.id = d_id;
-  a.tau_a = d_tau;
-  a.tau_b = d_tau ? d_tau + cells : nullptr;
-  a.dec = scratch + L.dec;
-  a.block_stats = (uint32_t*)(scratch + L.block_stats);
-  a.W = p->W;
-  a.H = p->H;
-  a.tiles_x = (p->W + kDecideTX - 1) / kDecideTX;
-  a.tiles_y = (p->H + kDecideTY - 1) / kDecideTY;
-  a.commit_bx = L.commit_bx;
-  a.commit_by = L.commit_by;
-  a.t = p->step0;
-  a.key0 = (uint32_t)p->seed;
-  a.key1 = (uint32_t)(p->seed >> 32);
+  Scenario& S = h->base;
+  memset(&S, 0, sizeof(S));
+  S.W = p->W;
+  S.H = p->H;
+  S.key0 = (uint32_t)p->seed;
+  S.key1 = (uint32_t)(p->seed >> 32);
   const float rho = p->rho;
-  a.keep = 1.0f - rho;
-  a.dtau = p->dtau;
-  a.eta_diag = heuristic(2.0, p->beta);
-  a.eta_lat = heuristic(5.0, p->beta);
-  a.alpha = p->alpha;
-  a.cross_a = p->cross_a;
-  a.cross_b = p->cross_b;
-  if (launch_count(a, s) != hipSuccess) {
+  S.keep = 1.0f - rho;
+  S.dtau = p->dtau;
+  S.eta_diag = heuristic(2.0, p->beta);
+  S.eta_lat = heuristic(5.0, p->beta);
+  S.alpha = p->alpha;
+  S.cross_a = p->cross_a;
+  S.cross_b = p->cross_b;
+  h->tiling[kModeLem] = default_tiling(false, cells);
+  h->tiling[kModeAco] = default_tiling(true, cells);
+  if (launch_count(d_code, p->W, p->H, p->cross_a, p->cross_b, h->stats, &h->stats_entries, s) != hipSuccess) {
     delete h;
     return SIM_EHIP;
   }
@@ -159,27 +282,43 @@ int sim_create(const sim_params* p, uint8_t* d_code, uint32_t* d_id, float* d_ta
   return SIM_OK;
 }
 
-static int step_n(sim_handle* h, int mode, int32_t nsteps, void* stream) {
+static int step_mode(sim_handle* h, int mode, int32_t nsteps, void* stream) {
   if (!h || nsteps < 0) return SIM_EINVAL;
-  if (mode == kModeAco && !h->tau) return SIM_ENOTAU;
-  hipStream_t s = (hipStream_t)stream;
-  for (int32_t i = 0; i < nsteps; ++i) {
-    h->args.t = h->t + (uint64_t)i;
-    if (launch_step(h->args, mode, i == nsteps - 1, s) != hipSuccess) return SIM_EHIP;
-  }
-  h->t += (uint64_t)nsteps;
+  if (mode == kModeAco && !h->user.tau) return SIM_ENOTAU;
+  return run_steps(h, mode, nsteps, (hipStream_t)stream, nullptr, nullptr, nullptr);
+}
+
+int sim_step_lem(sim_handle* h, int32_t nsteps, void* stream) { return step_mode(h, kModeLem, nsteps, stream); }
+
+int sim_step_aco(sim_handle* h, int32_t nsteps, void* stream) { return step_mode(h, kModeAco, nsteps, stream); }
+
+int sim_set_tiling(sim_handle* h, int32_t mode, int32_t nw, int32_t rows, int32_t steps_per_launch,
+                   int32_t threads) {
+  if (!h || (mode != kModeLem && mode != kModeAco)) return SIM_EINVAL;
+  const Tiling tl{nw, rows, steps_per_launch, threads};
+  if (!tiling_valid(tl, mode == kModeAco, max_dynamic_lds())) return SIM_EINVAL;
+  Scenario S = h->base;
+  set_geometry(S, tl);
+  if (S.tiles_x * S.tiles_y > h->stats_cap) return SIM_EINVAL;
+  h->tiling[mode] = tl;
   return SIM_OK;
 }
 
-int sim_step_lem(sim_handle* h, int32_t nsteps, void* stream) { return step_n(h, kModeLem, nsteps, stream); }
-
-int sim_step_aco(sim_handle* h, int32_t nsteps, void* stream) { return step_n(h, kModeAco, nsteps, stream); }
+int sim_get_tiling(sim_handle* h, int32_t mode, int32_t out[4]) {
+  if (!h || !out || (mode != kModeLem && mode != kModeAco)) return SIM_EINVAL;
+  const Tiling& tl = h->tiling[mode];
+  out[0] = tl.nw;
+  out[1] = tl.rows;
+  out[2] = tl.steps;
+  out[3] = tl.threads;
+  return SIM_OK;
+}
 
 int sim_stats(sim_handle* h, sim_stats_t* out, void* stream) {
   if (!h || !out) return SIM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  unsigned long long v[kStatFields];
-  if (launch_reduce_counts(h->args.block_stats, h->commit_blocks, h->totals, s) != hipSuccess) return SIM_EHIP;
+  unsigned long long v[kTileStatFields];
+  if (launch_reduce_counts(h->stats, h->stats_entries, h->totals, s) != hipSuccess) return SIM_EHIP;
   if (hipMemcpyAsync(v, h->totals, sizeof(v), hipMemcpyDeviceToHost, s) != hipSuccess) return SIM_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) return SIM_EHIP;
   out->step = h->t;
@@ -195,11 +334,11 @@ int sim_read_state(sim_handle* h, uint8_t* code, uint32_t* id, float* tau, void*
   if (!h) return SIM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   const size_t cells = (size_t)h->p.W * (size_t)h->p.H;
-  if (code && hipMemcpyAsync(code, h->code, cells, hipMemcpyDefault, s) != hipSuccess) return SIM_EHIP;
-  if (id && hipMemcpyAsync(id, h->id, cells * sizeof(uint32_t), hipMemcpyDefault, s) != hipSuccess)
+  if (code && hipMemcpyAsync(code, h->user.code, cells, hipMemcpyDefault, s) != hipSuccess) return SIM_EHIP;
+  if (id && hipMemcpyAsync(id, h->user.id, cells * sizeof(uint32_t), hipMemcpyDefault, s) != hipSuccess)
     return SIM_EHIP;
-  if (tau && h->tau &&
-      hipMemcpyAsync(tau, h->tau, 2 * cells * sizeof(float), hipMemcpyDefault, s) != hipSuccess)
+  if (tau && h->user.tau &&
+      hipMemcpyAsync(tau, h->user.tau, 2 * cells * sizeof(float), hipMemcpyDefault, s) != hipSuccess)
     return SIM_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) return SIM_EHIP;
   return SIM_OK;
@@ -207,39 +346,27 @@ int sim_read_state(sim_handle* h, uint8_t* code, uint32_t* id, float* tau, void*
 
 int sim_step_timed(sim_handle* h, int32_t mode, int32_t nsteps, void* stream, double* kernel_ms,
                    int64_t* launches, int32_t max_kinds) {
-  if (!h || nsteps < 0 || !kernel_ms || !launches || max_kinds < kKernelKinds) return SIM_EINVAL;
+  if (!h || nsteps < 0 || !kernel_ms || !launches || max_kinds < 2) return SIM_EINVAL;
   if (mode != kModeLem && mode != kModeAco) return SIM_EINVAL;
-  if (mode == kModeAco && !h->tau) return SIM_ENOTAU;
-  hipStream_t s = (hipStream_t)stream;
-  hipEvent_t ev[kKernelKinds + 1];
-  int made = 0;
-  int rc = SIM_OK;
-  for (; made < kKernelKinds + 1; ++made)
-    if (hipEventCreate(&ev[made]) != hipSuccess) {
-      rc = SIM_EHIP;
-      break;
-    }
-  for (int32_t i = 0; rc == SIM_OK && i < nsteps; ++i) {
-    h->args.t = h->t;
-    if (launch_step(h->args, mode, i == nsteps - 1, s, ev) != hipSuccess ||
-        hipEventSynchronize(ev[kKernelKinds]) != hipSuccess) {
-      rc = SIM_EHIP;
-      break;
-    }
-    h->t += 1;
-    for (int k = 0; k < kKernelKinds; ++k) {
-      float ms = 0.0f;
-      if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess) rc = SIM_EHIP;
-      kernel_ms[k] += ms;
-      launches[k] += 1;
-    }
+  if (mode == kModeAco && !h->user.tau) return SIM_ENOTAU;
+  hipEvent_t ev[2];
+  if (hipEventCreate(&ev[0]) != hipSuccess) return SIM_EHIP;
+  if (hipEventCreate(&ev[1]) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return SIM_EHIP;
   }
-  for (int k = 0; k < made; ++k) (void)hipEventDestroy(ev[k]);
-  return rc == SIM_OK ? kKernelKinds : rc;
+  const int rc = run_steps(h, mode, nsteps, (hipStream_t)stream, ev, kernel_ms, launches);
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  return rc == SIM_OK ? 2 : rc;
 }
 
 const char* sim_kernel_name(int32_t kind) {
-  return (kind >= 0 && kind < kKernelKinds) ? kKernelNames[kind] : "";
+  switch (kind) {
+    case 0: return "tile_kernel";
+    case 1: return "copy_back";
+    default: return "";
+  }
 }
 
 void sim_destroy(sim_handle* h) { delete h; }

@@ -6,58 +6,45 @@
 #include <stdint.h>
 
 #include "rules.hpp"
+#include "tile_engine.hpp"
 
 namespace pedsim {
 
 constexpr int kModeLem = 0;
 constexpr int kModeAco = 1;
 
-// decide: a workgroup owns a kDecideTX x kDecideTY tile.
-constexpr int kDecideTX = 64;
-constexpr int kDecideTY = 8;
-constexpr int kDecideThreads = 256;
-
-// commit: a workgroup owns a kCommitTX x kCommitTY block, one cell per lane.
-constexpr int kCommitTX = 64;
-constexpr int kCommitTY = 4;
-constexpr int kCommitThreads = kCommitTX * kCommitTY;
-
-// per-workgroup counters: agents A, agents B, crossed A, crossed B, moved
-constexpr int kStatFields = 5;
-
-struct StepArgs {
-  uint8_t* code;
-  uint32_t* id;
-  float* tau_a;
-  float* tau_b;
-  uint8_t* dec;           // one decision byte per cell (scratch)
-  uint32_t* block_stats;  // kStatFields per commit workgroup (scratch)
-  int W, H;
-  int tiles_x, tiles_y;   // decide tiles
-  int commit_bx, commit_by;
-  uint64_t t;             // index of the step being run
-  uint32_t key0, key1;    // Philox key (seed)
-  float keep;             // fl(1 - rho)
-  float dtau;
-  float eta_diag, eta_lat;  // eta^beta of the diagonal and lateral candidates
-  int alpha;
-  int cross_a, cross_b;
+// Tiling of one scenario for the tile engine: regions of 64*nw columns x
+// rows, advanced `steps` steps per launch (halo 3*steps), `threads` per
+// workgroup.
+struct Tiling {
+  int nw;       // 1 or 2 words per row
+  int rows;     // region rows, <= threads
+  int steps;    // steps per launch (>= 1)
+  int threads;  // workgroup size, multiple of 64, <= 1024
 };
 
-// Kernel kinds of one step, in launch order.
-constexpr int kKernelKinds = 2;
-extern const char* const kKernelNames[kKernelKinds];
+// Smallest tile interior the host accepts (bounds the per-tile counter array).
+constexpr int kMinInteriorX = 16;
+constexpr int kMinInteriorY = 8;
 
-// Launch one step. With `ev` non-null (kKernelKinds + 1 events), event i is
-// recorded before kernel i and the last one after the final kernel.
-hipError_t launch_step(const StepArgs& a, int mode, int write_stats, hipStream_t s,
-                       hipEvent_t* ev = nullptr);
-hipError_t launch_count(const StepArgs& a, hipStream_t s);
-hipError_t launch_reduce_counts(const uint32_t* block_stats, int nblocks, unsigned long long* out,
-                                hipStream_t s);
+size_t tile_lds_bytes(const Tiling& tl, bool aco);
+bool tiling_valid(const Tiling& tl, bool aco, int max_lds);
+
+// One launch of the tile engine over every tile of S.
+hipError_t launch_tiles(const Scenario& S, const Tiling& tl, int mode, uint64_t t0, int steps, int last,
+                        hipStream_t s);
+
+// Counters of the current planes without stepping: kTileStatFields per
+// workgroup of the count kernel; returns the number of entries written.
+hipError_t launch_count(const uint8_t* code, int W, int H, int cross_a, int cross_b, uint32_t* stats,
+                        int* entries, hipStream_t s);
+
+hipError_t launch_reduce_counts(const uint32_t* stats, int entries, unsigned long long* out, hipStream_t s);
 hipError_t launch_validate(const uint8_t* code, const uint32_t* id, const float* tau, size_t cells,
                            unsigned long long* counters, hipStream_t s);
 hipError_t launch_validate_ids(const uint32_t* id, size_t cells, uint32_t n, uint32_t* bitmap,
                                unsigned long long* counters, hipStream_t s);
+
+int max_dynamic_lds();
 
 }  // namespace pedsim

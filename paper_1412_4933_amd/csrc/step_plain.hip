@@ -1,251 +1,114 @@
-// Single-scenario step kernels for gfx950.
-//
-// One step of the paper's update (Sec. IV.b-d) runs as two kernels:
-//
-//   decide  (request + resolve, the paper's initial-calculation and
-//            tour-construction phases plus the gather half of its movement
-//            phase): a workgroup stages the code plane of its tile plus a
-//            2-cell halo in LDS, computes the request of every agent of the
-//            tile plus a 1-cell ring, then every empty cell of the tile
-//            gathers the neighbours whose request points at it and keeps the
-//            lowest (Philox word 0, agent number). It writes one decision byte
-//            per cell (request code on agent cells; winner slot and group on
-//            empty cells) and the winner's id into the receiving cell.
-//   commit  (the rest of the movement phase + pheromone update): each cell
-//            reads its own code and decision byte; a receiving cell takes the
-//            winner's group, a winning agent's cell empties (it checks its
-//            target's winner slot), then both pheromone planes evaporate and
-//            receive the deposit (eq. 3 then eq. 4), and wave64 ballots count
-//            agents, crossings and moves per workgroup.
-//
-// Both kernels update the caller's planes in place without races: decide
-// reads codes everywhere and ids only on agent cells, and writes ids only on
-// cells that are empty at t; commit touches only its own cell's code, id and
-// pheromone and reads decision bytes, which nobody writes during commit.
+// Single-scenario kernels for gfx950: the tile-engine launch (k steps per
+// launch, one workgroup per tile), plus counting, reduction and create-time
+// validation.
 #include "pedsim_internal.hpp"
 
 namespace pedsim {
 
-// ---------------------------------------------------------------------------
-// decide
-// ---------------------------------------------------------------------------
-constexpr int kHX = kDecideTX + 4;  // staged code region (2-cell halo)
-constexpr int kHY = kDecideTY + 4;
-constexpr int kRX = kDecideTX + 2;  // request ring (1-cell halo)
-constexpr int kRY = kDecideTY + 2;
-
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD one
+// contiguous run of row-major tiles so shared halo lines stay in its L2.
 __device__ __forceinline__ int tile_of_block(int bid, int ntiles) {
-  // Workgroups are dealt round-robin to the 8 XCDs; give each XCD one
-  // contiguous run of row-major tiles so halo lines are reused in its L2.
   const int per = (ntiles + 7) >> 3;
   return (bid & 7) * per + (bid >> 3);
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kDecideThreads) void decide_kernel(StepArgs a) {
-  __shared__ uint8_t s_code[kHY * kHX];
-  __shared__ uint8_t s_req[kRY * kRX];
+template <int NW, int MODE>
+__global__ __launch_bounds__(1024) void tile_kernel(Scenario S, int R, uint64_t t0, int steps, int last) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int ntiles = S.tiles_x * S.tiles_y;
+  const int tile = tile_of_block(blockIdx.x, ntiles);
+  if (tile >= ntiles) return;
+  advance_tile<NW, MODE>(S, smem, R, tile % S.tiles_x, tile / S.tiles_x, tile, t0, steps, last != 0);
+}
 
-  const int tile = tile_of_block(blockIdx.x, a.tiles_x * a.tiles_y);
-  if (tile >= a.tiles_x * a.tiles_y) return;
-  const int x0 = (tile % a.tiles_x) * kDecideTX;
-  const int y0 = (tile / a.tiles_x) * kDecideTY;
-  const int W = a.W, H = a.H;
+size_t tile_lds_bytes(const Tiling& tl, bool aco) {
+  return tl.nw == 1 ? Layout<1>{tl.rows, aco}.bytes() : Layout<2>{tl.rows, aco}.bytes();
+}
 
-  for (int i = threadIdx.x; i < kHY * kHX; i += kDecideThreads) {
-    const int gx = x0 + (i % kHX) - 2;
-    const int gy = y0 + (i / kHX) - 2;
-    uint8_t v = kWall;
-    if (gx >= 0 && gx < W && gy >= 0 && gy < H) v = a.code[(size_t)gy * W + gx];
-    s_code[i] = v;
+bool tiling_valid(const Tiling& tl, bool aco, int max_lds) {
+  if (tl.nw != 1 && tl.nw != 2) return false;
+  if (tl.steps < 1 || tl.threads < 64 || tl.threads > 1024 || tl.threads % 64) return false;
+  if (tl.rows < 1 || tl.rows > 1023) return false;
+  if (64 * tl.nw - 6 * tl.steps < kMinInteriorX || tl.rows - 6 * tl.steps < kMinInteriorY) return false;
+  return tile_lds_bytes(tl, aco) <= (size_t)max_lds;
+}
+
+int max_dynamic_lds() {
+  static int cached = -1;
+  if (cached < 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      v = 65536;
+    cached = v;
   }
-  __syncthreads();
+  return cached;
+}
 
-  // Requests on the tile plus a 1-cell ring, from the snapshot of time t.
-  for (int i = threadIdx.x; i < kRY * kRX; i += kDecideThreads) {
-    const int rx = i % kRX, ry = i / kRX;
-    const int c = (ry + 1) * kHX + (rx + 1);
-    const int g = s_code[c];
-    int req = kReqNone;
-    if (g == kGroupA || g == kGroupB) {
-      const int d = g == kGroupA ? 1 : -1;
-      if (s_code[c + d] == kEmpty) {
-        req = kReqF;
-      } else {
-        const unsigned avail = (unsigned)(s_code[c - kHX + d] == kEmpty) |
-                               ((unsigned)(s_code[c + kHX + d] == kEmpty) << 1) |
-                               ((unsigned)(s_code[c - kHX] == kEmpty) << 2) |
-                               ((unsigned)(s_code[c + kHX] == kEmpty) << 3);
-        if (avail) {
-          const int gx = x0 + rx - 1, gy = y0 + ry - 1;
-          const size_t gi = (size_t)gy * W + gx;
-          const Words w = agent_words(a.id[gi] - 1u, a.t, a.key0, a.key1);
-          if (MODE == kModeLem) {
-            req = lem_choose(avail, w.w1, w.w2);
-          } else {
-            const float* plane = g == kGroupA ? a.tau_a : a.tau_b;
-            float tau[4];
-            tau[0] = (avail & 1u) ? plane[gi - W + d] : 0.0f;
-            tau[1] = (avail & 2u) ? plane[gi + W + d] : 0.0f;
-            tau[2] = (avail & 4u) ? plane[gi - W] : 0.0f;
-            tau[3] = (avail & 8u) ? plane[gi + W] : 0.0f;
-            req = aco_choose(avail, tau, a.alpha, a.eta_diag, a.eta_lat, w.w1, w.w2);
-          }
-        }
-      }
-    }
-    s_req[i] = (uint8_t)req;
+template <int NW, int MODE>
+static hipError_t launch_one(const Scenario& S, const Tiling& tl, uint64_t t0, int steps, int last, hipStream_t s) {
+  const size_t lds = Layout<NW>{tl.rows, MODE == kModeAco}.bytes();
+  static bool attr_done = false;
+  if (!attr_done) {
+    (void)hipFuncSetAttribute((const void*)tile_kernel<NW, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              max_dynamic_lds());
+    attr_done = true;
   }
-  __syncthreads();
+  const int ntiles = S.tiles_x * S.tiles_y;
+  const int blocks = ((ntiles + 7) / 8) * 8;
+  tile_kernel<NW, MODE><<<blocks, tl.threads, lds, s>>>(S, tl.rows, t0, steps, last);
+  return hipGetLastError();
+}
 
-  // Resolve: every cell of the tile that is empty at t gathers its requesters.
-  for (int i = threadIdx.x; i < kDecideTY * kDecideTX; i += kDecideThreads) {
-    const int lx = i % kDecideTX, ly = i / kDecideTX;
-    const int gx = x0 + lx, gy = y0 + ly;
-    if (gx >= W || gy >= H) continue;
-    const size_t gi = (size_t)gy * W + gx;
-    const int c = (ly + 2) * kHX + (lx + 2);
-    const int g = s_code[c];
-    uint8_t dec = 0;
-    if (g == kGroupA || g == kGroupB) {
-      dec = s_req[(ly + 1) * kRX + (lx + 1)];
-    } else if (g == kEmpty) {
-      int count = 0, win_dx = 0, win_dy = 0;
-      unsigned cand = 0;  // bit (slot-1) set for each requester
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy) {
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          if (dx == 0 && dy == 0) continue;
-          const int ng = s_code[c + dy * kHX + dx];
-          if (ng != kGroupA && ng != kGroupB) continue;
-          const int r = s_req[(ly + 1 + dy) * kRX + (lx + 1 + dx)];
-          if (r == kReqNone) continue;
-          const int d = ng == kGroupA ? 1 : -1;
-          if (dx + req_dx(r, d) == 0 && dy + req_dy(r) == 0) {
-            count += 1;
-            cand |= 1u << (slot_of(dx, dy) - 1);
-            win_dx = dx;
-            win_dy = dy;
-          }
-        }
-      }
-      if (count > 1) {
-        // Several requesters: lowest (word 0, agent number) wins.
-        uint32_t best_t = 0xFFFFFFFFu, best_k = 0xFFFFFFFFu;
-        bool have = false;
-        while (cand) {
-          const int s = __ffs(cand) - 1;
-          cand &= cand - 1;
-          const int dx = s % 3 - 1, dy = s / 3 - 1;
-          const uint32_t k = a.id[gi + (ptrdiff_t)dy * W + dx] - 1u;
-          const uint32_t tk = agent_words(k, a.t, a.key0, a.key1).w0;
-          if (!have || tk < best_t || (tk == best_t && k < best_k)) {
-            have = true;
-            best_t = tk;
-            best_k = k;
-            win_dx = dx;
-            win_dy = dy;
-          }
-        }
-      }
-      if (count > 0) {
-        const size_t src = gi + (ptrdiff_t)win_dy * W + win_dx;
-        const int wg = s_code[c + win_dy * kHX + win_dx];
-        dec = (uint8_t)((wg << 4) | slot_of(win_dx, win_dy));
-        a.id[gi] = a.id[src];
-      }
-    }
-    a.dec[gi] = dec;
-  }
+hipError_t launch_tiles(const Scenario& S, const Tiling& tl, int mode, uint64_t t0, int steps, int last,
+                        hipStream_t s) {
+  if (tl.nw == 1)
+    return mode == kModeLem ? launch_one<1, kModeLem>(S, tl, t0, steps, last, s)
+                            : launch_one<1, kModeAco>(S, tl, t0, steps, last, s);
+  return mode == kModeLem ? launch_one<2, kModeLem>(S, tl, t0, steps, last, s)
+                          : launch_one<2, kModeAco>(S, tl, t0, steps, last, s);
 }
 
 // ---------------------------------------------------------------------------
-// commit + pheromone + counters
+// counters without stepping
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void block_counts(bool agent_a, bool agent_b, bool cross_a, bool cross_b,
-                                             bool moved, uint32_t* out) {
-  __shared__ uint32_t s_cnt[kCommitThreads / 64][kStatFields];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const uint32_t v[kStatFields] = {
-      (uint32_t)__popcll(__ballot(agent_a)), (uint32_t)__popcll(__ballot(agent_b)),
-      (uint32_t)__popcll(__ballot(cross_a)), (uint32_t)__popcll(__ballot(cross_b)),
-      (uint32_t)__popcll(__ballot(moved))};
-  if (lane == 0) {
-#pragma unroll
-    for (int f = 0; f < kStatFields; ++f) s_cnt[wave][f] = v[f];
-  }
-  __syncthreads();
-  if (threadIdx.x < kStatFields) {
-    uint32_t s = 0;
-#pragma unroll
-    for (int w = 0; w < kCommitThreads / 64; ++w) s += s_cnt[w][threadIdx.x];
-    out[threadIdx.x] = s;
-  }
-}
+constexpr int kCountTX = 64, kCountTY = 4;
 
-template <int MODE>
-__global__ __launch_bounds__(kCommitThreads) void commit_kernel(StepArgs a, int write_stats) {
-  const int x = blockIdx.x * kCommitTX + (threadIdx.x % kCommitTX);
-  const int y = blockIdx.y * kCommitTY + (threadIdx.x / kCommitTX);
-  const int W = a.W, H = a.H;
-  const bool in = x < W && y < H;
-  int g_new = kWall;
-  bool moved_in = false;
-  if (in) {
-    const size_t gi = (size_t)y * W + x;
-    const int g = a.code[gi];
-    const int dec = a.dec[gi];
-    g_new = g;
-    if (g == kEmpty) {
-      if (dec & 0xF) {
-        g_new = dec >> 4;
-        moved_in = true;
-      }
-    } else if ((g == kGroupA || g == kGroupB) && dec != kReqNone) {
-      const int d = g == kGroupA ? 1 : -1;
-      const int dx = req_dx(dec, d), dy = req_dy(dec);
-      const int back = a.dec[gi + (ptrdiff_t)dy * W + dx] & 0xF;
-      if (back == slot_of(-dx, -dy)) {
-        g_new = kEmpty;
-        a.id[gi] = 0u;
-      }
-    }
-    if (g_new != g) a.code[gi] = (uint8_t)g_new;
-    if (MODE == kModeAco) {
-      float va = a.keep * a.tau_a[gi];
-      float vb = a.keep * a.tau_b[gi];
-      if (g_new == kGroupA) va = va + a.dtau;
-      if (g_new == kGroupB) vb = vb + a.dtau;
-      a.tau_a[gi] = va;
-      a.tau_b[gi] = vb;
-    }
-  }
-  if (write_stats) {
-    const int blin = blockIdx.y * gridDim.x + blockIdx.x;
-    block_counts(g_new == kGroupA, g_new == kGroupB, g_new == kGroupA && x >= W - a.cross_b,
-                 g_new == kGroupB && x < a.cross_a, moved_in, a.block_stats + (size_t)blin * kStatFields);
-  }
-}
-
-// Counters of the current planes without stepping (used after create).
-__global__ __launch_bounds__(kCommitThreads) void count_kernel(StepArgs a) {
-  const int x = blockIdx.x * kCommitTX + (threadIdx.x % kCommitTX);
-  const int y = blockIdx.y * kCommitTY + (threadIdx.x / kCommitTX);
+__global__ __launch_bounds__(256) void count_kernel(const uint8_t* code, int W, int H, int cross_a, int cross_b,
+                                                    uint32_t* stats) {
+  __shared__ uint32_t s_cnt[kTileStatFields];
+  const int x = blockIdx.x * kCountTX + (threadIdx.x % kCountTX);
+  const int y = blockIdx.y * kCountTY + (threadIdx.x / kCountTX);
   int g = kWall;
-  if (x < a.W && y < a.H) g = a.code[(size_t)y * a.W + x];
+  if (x < W && y < H) g = code[(size_t)y * W + x];
+  if (threadIdx.x < kTileStatFields) s_cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  const uint32_t v[kTileStatFields] = {(uint32_t)__popcll(__ballot(g == kGroupA)),
+                                       (uint32_t)__popcll(__ballot(g == kGroupB)),
+                                       (uint32_t)__popcll(__ballot(g == kGroupA && x >= W - cross_b)),
+                                       (uint32_t)__popcll(__ballot(g == kGroupB && x < cross_a)), 0u};
+  if ((threadIdx.x & 63) == 0)
+    for (int f = 0; f < kTileStatFields; ++f) atomicAdd(&s_cnt[f], v[f]);
+  __syncthreads();
   const int blin = blockIdx.y * gridDim.x + blockIdx.x;
-  block_counts(g == kGroupA, g == kGroupB, g == kGroupA && x >= a.W - a.cross_b,
-               g == kGroupB && x < a.cross_a, false, a.block_stats + (size_t)blin * kStatFields);
+  if (threadIdx.x < kTileStatFields) stats[(size_t)blin * kTileStatFields + threadIdx.x] = s_cnt[threadIdx.x];
 }
 
-// Sum the per-workgroup counters into kStatFields 64-bit totals.
-__global__ __launch_bounds__(256) void reduce_counts_kernel(const uint32_t* block_stats, int nblocks,
+hipError_t launch_count(const uint8_t* code, int W, int H, int cross_a, int cross_b, uint32_t* stats, int* entries,
+                        hipStream_t s) {
+  const dim3 grid((W + kCountTX - 1) / kCountTX, (H + kCountTY - 1) / kCountTY);
+  *entries = (int)(grid.x * grid.y);
+  count_kernel<<<grid, kCountTX * kCountTY, 0, s>>>(code, W, H, cross_a, cross_b, stats);
+  return hipGetLastError();
+}
+
+// Sum per-tile counters into kTileStatFields 64-bit totals.
+__global__ __launch_bounds__(256) void reduce_counts_kernel(const uint32_t* stats, int entries,
                                                             unsigned long long* out) {
   __shared__ unsigned long long s[256];
-  for (int f = 0; f < kStatFields; ++f) {
+  for (int f = 0; f < kTileStatFields; ++f) {
     unsigned long long acc = 0;
-    for (int b = threadIdx.x; b < nblocks; b += 256) acc += block_stats[(size_t)b * kStatFields + f];
+    for (int b = threadIdx.x; b < entries; b += 256) acc += stats[(size_t)b * kTileStatFields + f];
     s[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -255,6 +118,11 @@ __global__ __launch_bounds__(256) void reduce_counts_kernel(const uint32_t* bloc
     if (threadIdx.x == 0) out[f] = s[0];
     __syncthreads();
   }
+}
+
+hipError_t launch_reduce_counts(const uint32_t* stats, int entries, unsigned long long* out, hipStream_t s) {
+  reduce_counts_kernel<<<1, 256, 0, s>>>(stats, entries, out);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -301,40 +169,6 @@ __global__ __launch_bounds__(256) void validate_ids_kernel(const uint32_t* id, s
     if (old & bit) bad = 1;
   }
   if (bad) atomicOr(&counters[2], 1ull);
-}
-
-// ---------------------------------------------------------------------------
-// host launchers
-// ---------------------------------------------------------------------------
-const char* const kKernelNames[kKernelKinds] = {"decide", "commit"};
-
-hipError_t launch_step(const StepArgs& a, int mode, int write_stats, hipStream_t s, hipEvent_t* ev) {
-  const int ntiles = a.tiles_x * a.tiles_y;
-  const int nblocks = ((ntiles + 7) / 8) * 8;
-  const dim3 cgrid(a.commit_bx, a.commit_by);
-  if (ev) (void)hipEventRecord(ev[0], s);
-  if (mode == kModeLem)
-    decide_kernel<kModeLem><<<nblocks, kDecideThreads, 0, s>>>(a);
-  else
-    decide_kernel<kModeAco><<<nblocks, kDecideThreads, 0, s>>>(a);
-  if (ev) (void)hipEventRecord(ev[1], s);
-  if (mode == kModeLem)
-    commit_kernel<kModeLem><<<cgrid, kCommitThreads, 0, s>>>(a, write_stats);
-  else
-    commit_kernel<kModeAco><<<cgrid, kCommitThreads, 0, s>>>(a, write_stats);
-  if (ev) (void)hipEventRecord(ev[2], s);
-  return hipGetLastError();
-}
-
-hipError_t launch_count(const StepArgs& a, hipStream_t s) {
-  count_kernel<<<dim3(a.commit_bx, a.commit_by), kCommitThreads, 0, s>>>(a);
-  return hipGetLastError();
-}
-
-hipError_t launch_reduce_counts(const uint32_t* block_stats, int nblocks, unsigned long long* out,
-                                hipStream_t s) {
-  reduce_counts_kernel<<<1, 256, 0, s>>>(block_stats, nblocks, out);
-  return hipGetLastError();
 }
 
 hipError_t launch_validate(const uint8_t* code, const uint32_t* id, const float* tau, size_t cells,

@@ -66,6 +66,10 @@ def lib() -> ctypes.CDLL:
         L.sim_read_state.argtypes = [vp, vp, vp, vp, vp]
         L.sim_step_timed.argtypes = [vp, i32, i32, vp, P(ctypes.c_double), P(ctypes.c_int64), i32]
         L.sim_step_timed.restype = ctypes.c_int
+        L.sim_set_tiling.argtypes = [vp, i32, i32, i32, i32, i32]
+        L.sim_set_tiling.restype = ctypes.c_int
+        L.sim_get_tiling.argtypes = [vp, i32, P(ctypes.c_int32)]
+        L.sim_get_tiling.restype = ctypes.c_int
         L.sim_kernel_name.argtypes = [i32]
         L.sim_kernel_name.restype = ctypes.c_char_p
         L.sim_destroy.argtypes = [vp]
@@ -168,6 +172,17 @@ def sim_step_timed(h, mode: int, nsteps: int, stream=None) -> dict:
     return {lib().sim_kernel_name(k).decode(): (float(ms[k]), int(cnt[k])) for k in range(rc)}
 
 
+def sim_set_tiling(h, mode: int, nw: int, rows: int, steps_per_launch: int, threads: int) -> None:
+    _check(lib().sim_set_tiling(h, int(mode), int(nw), int(rows), int(steps_per_launch), int(threads)),
+           "sim_set_tiling")
+
+
+def sim_get_tiling(h, mode: int):
+    out = (ctypes.c_int32 * 4)()
+    _check(lib().sim_get_tiling(h, int(mode), out), "sim_get_tiling")
+    return tuple(int(v) for v in out)
+
+
 def sim_kernel_name(kind: int) -> str:
     return lib().sim_kernel_name(int(kind)).decode()
 
@@ -216,6 +231,12 @@ class Sim:
 
     def stats(self) -> dict:
         return sim_stats(self.h, self.stream)
+
+    def set_tiling(self, mode: int, nw: int, rows: int, steps_per_launch: int, threads: int) -> None:
+        sim_set_tiling(self.h, mode, nw, rows, steps_per_launch, threads)
+
+    def tiling(self, mode: int):
+        return sim_get_tiling(self.h, mode)
 
     def state(self):
         """(code, ids, tau) copied to host numpy arrays."""

@@ -249,3 +249,32 @@ def test_aco_without_pheromone_refused(pedsim):
     assert e.value.code == pedsim.SIM_ENOTAU
     sim.step(3, S.MODE_LEM)
     sim.close()
+
+
+TILINGS = [(1, 32, 1, 256), (1, 48, 2, 512), (1, 64, 3, 1024), (2, 40, 1, 64 * 1), (2, 64, 2, 1024),
+           (2, 64, 4, 1024), (1, 96, 2, 128)]
+
+
+@pytest.mark.parametrize("mode", [S.MODE_LEM, S.MODE_ACO])
+def test_results_do_not_depend_on_tiling(pedsim, mode):
+    """Every allowed tile shape, region height, steps per launch and
+    workgroup size gives the oracle's result bit for bit."""
+    scn = S.make_scenario(333, 150, 2500, 2400, band_a=14, seed=19, mode=mode,
+                          obstacle_frac=0.04, with_tau=True)
+    st = oracle.State.from_scenario(scn)
+    st.run(mode, 37)
+    ran = 0
+    for tl in TILINGS:
+        sim = pedsim.Sim(scn)
+        try:
+            sim.set_tiling(mode, *tl)
+        except pedsim.SimError:
+            sim.close()
+            continue  # shape not allowed on this device (LDS) or too small
+        say("tiling", mode, tl)
+        sim.step(10, mode)
+        sim.step(27, mode)
+        assert_same(sim, st, f"tiling {tl}")
+        sim.close()
+        ran += 1
+    assert ran >= 4
