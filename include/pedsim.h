@@ -156,6 +156,55 @@ const char* sim_kernel_name(int32_t kind);
 /* Release a handle (not the caller's buffers). NULL is ignored. */
 void sim_destroy(sim_handle* h);
 
+/*
+ * Batched form: many independent scenarios (any sizes, LEM or ACO each)
+ * advanced together by one persistent kernel per launch, whose work items are
+ * (scenario, tile) pairs claimed from a counter; a call's launch sequence is
+ * captured once in a hipGraph and replayed. Every scenario's results are
+ * bit-identical to running it alone through sim_step_lem / sim_step_aco.
+ */
+typedef struct sim_batch sim_batch;
+
+/* Bytes of device workspace a batch of `capacity` (1..65535) scenarios needs. */
+int sim_batch_workspace_bytes(int32_t capacity, size_t* out);
+
+/* Create an empty batch over a caller-owned device workspace. The batch
+ * also holds a small pinned host staging buffer of its own. */
+int sim_batch_create(int32_t capacity, void* d_workspace, size_t workspace_bytes, sim_batch** out);
+
+/* Add a scenario: same planes, scratch (sim_scratch_bytes) and validation as
+ * sim_create; mode (SIM_MODE_LEM / SIM_MODE_ACO) is fixed for the scenario.
+ * Writes its slot index. SIM_EFULL when no slot is free. Synchronises. */
+int sim_batch_add(sim_batch* b, const sim_params* p, int32_t mode, uint8_t* d_code, uint32_t* d_id, float* d_tau,
+                  void* d_scratch, size_t scratch_bytes, void* stream, int32_t* slot);
+
+/* Free a slot; the scenario's buffers are the caller's again once the stream
+ * has passed the calls that used them. */
+int sim_batch_remove(sim_batch* b, int32_t slot);
+
+/* Advance slot i by steps[i] >= 0 steps, i < n (0 leaves it idle), in shared
+ * launches; asynchronous. Every stepped slot's planes hold its new state once
+ * the stream has reached the end of the call. */
+int sim_batch_step_slots(sim_batch* b, const int32_t* steps, int32_t n, void* stream);
+
+/* Advance every scenario of the batch by nsteps. */
+int sim_batch_step(sim_batch* b, int32_t nsteps, void* stream);
+
+/* Counters of one scenario after its last completed step; synchronises. */
+int sim_batch_stats(sim_batch* b, int32_t slot, sim_stats_t* out, void* stream);
+
+/* Launch shape (results never depend on it): tiling as for sim_set_tiling,
+ * wgs_per_cu persistent workgroups per compute unit (1..32), and whether
+ * calls replay captured hipGraphs (1) or launch directly (0).
+ * sim_batch_get_tuning writes {nw, rows, steps_per_launch, threads,
+ * wgs_per_cu, use_graph}. */
+int sim_batch_set_tuning(sim_batch* b, int32_t nw, int32_t rows, int32_t steps_per_launch, int32_t threads,
+                         int32_t wgs_per_cu, int32_t use_graph);
+int sim_batch_get_tuning(sim_batch* b, int32_t out[6]);
+
+/* Release the batch (not the caller's buffers). NULL is ignored. */
+void sim_batch_destroy(sim_batch* b);
+
 /* Static text for a SIM_* code. */
 const char* sim_strerror(int code);
 

@@ -1,0 +1,378 @@
+// C ABI of the batched form (declared in include/pedsim.h).
+//
+// A batch holds up to `capacity` independent scenarios, each with its own
+// caller-owned planes and scratch. A step call advances each scenario by its
+// own number of steps in shared launches of the persistent batch kernel: the
+// host writes the per-scenario descriptors and the per-launch work tables
+// into a pinned staging buffer, copies them into the caller-owned device
+// workspace with one asynchronous copy, and replays a captured hipGraph of
+// the launch sequence (one graph per launch count, instantiated on first
+// use). Calls with more launches than one graph holds are split.
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "pedsim.h"
+#include "pedsim_internal.hpp"
+
+using namespace pedsim;
+
+namespace {
+
+struct HostSlot {
+  bool used = false;
+  sim_params p;
+  int mode = 0;
+  Planes user{}, shadow{};
+  ScratchLayout L{};
+  Scenario S{};
+  uint32_t* stats = nullptr;
+  unsigned long long* totals = nullptr;
+  int stats_entries = 0;
+  uint64_t t = 0;
+};
+
+// Byte offsets of the tables inside the workspace (and the staging copy).
+struct BatchLayout {
+  size_t slots, entries, counts, totals, counters, upload, total;
+};
+
+BatchLayout batch_layout(int capacity) {
+  BatchLayout L;
+  L.slots = 0;
+  L.entries = L.slots + round_up((size_t)capacity * sizeof(BatchSlot));
+  L.counts = L.entries + round_up((size_t)kBatchMaxLaunches * capacity * sizeof(BatchEntry));
+  L.totals = L.counts + round_up((size_t)kBatchMaxLaunches * sizeof(int));
+  L.upload = L.totals + round_up((size_t)kBatchMaxLaunches * sizeof(int));  // bytes copied per call
+  L.counters = L.upload;
+  L.total = L.counters + round_up((size_t)kBatchMaxLaunches * sizeof(unsigned));
+  return L;
+}
+
+}  // namespace
+
+struct sim_batch {
+  int capacity;
+  uint8_t* ws;
+  BatchLayout L;
+  uint8_t* staging;  // pinned host copy of the uploaded tables
+  hipEvent_t uploaded;
+  bool upload_pending;
+  hipStream_t capture;  // private stream the launch sequences are captured on
+  std::vector<HostSlot> slots;
+  Tiling tl;
+  int wgs_per_cu;
+  int use_graph;
+  hipGraphExec_t graphs[kBatchMaxLaunches + 1];
+
+  BatchPlan plan() const {
+    BatchPlan P;
+    P.slots = (const BatchSlot*)(ws + L.slots);
+    P.entries = (const BatchEntry*)(ws + L.entries);
+    P.counts = (const int*)(ws + L.counts);
+    P.totals = (const int*)(ws + L.totals);
+    P.counters = (unsigned*)(ws + L.counters);
+    P.capacity = capacity;
+    P.k = tl.steps;
+    P.rows = tl.rows;
+    return P;
+  }
+  void drop_graphs() {
+    for (int i = 0; i <= kBatchMaxLaunches; ++i)
+      if (graphs[i]) {
+        (void)hipGraphExecDestroy(graphs[i]);
+        graphs[i] = nullptr;
+      }
+  }
+};
+
+namespace {
+
+Tiling default_batch_tiling() {
+  static const Tiling opts[] = {{1, 64, 2, 512}, {1, 32, 2, 512}, {1, 32, 1, 256}};
+  for (const Tiling& t : opts)
+    if (tiling_valid(t, true, max_dynamic_lds() - kBatchItemBytes)) return t;
+  return opts[2];
+}
+
+bool slot_geometry(const Tiling& tl, HostSlot& hs) {
+  Scenario S = base_scenario(&hs.p);
+  set_geometry(S, tl);
+  if (S.tiles_x * S.tiles_y > hs.L.stats_cap) return false;
+  S.tile_stats = hs.stats;
+  hs.S = S;
+  return true;
+}
+
+// Enqueue one call's launch sequence on stream s: replay a cached graph
+// (captured once on the batch's private stream; the caller's stream may be
+// the null stream, which cannot be captured) or launch directly.
+int enqueue_sequence(sim_batch* b, int launches, hipStream_t s) {
+  const BatchPlan P = b->plan();
+  const int grid = device_cu_count() * b->wgs_per_cu;
+  auto issue = [&](hipStream_t on) -> hipError_t {
+    hipError_t e = launch_batch_reset(P, launches, on);
+    for (int j = 0; e == hipSuccess && j < launches; ++j) e = launch_batch(P, b->tl, j, grid, on);
+    if (e == hipSuccess) e = launch_batch_copyback(P, b->capacity, on);
+    return e;
+  };
+  if (!b->use_graph) return issue(s) == hipSuccess ? SIM_OK : SIM_EHIP;
+  if (!b->graphs[launches]) {
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return SIM_EHIP;
+    const hipError_t e = issue(b->capture);
+    const hipError_t e2 = hipStreamEndCapture(b->capture, &g);
+    if (e != hipSuccess || e2 != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return SIM_EHIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e3 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) return SIM_EHIP;
+    b->graphs[launches] = exec;
+  }
+  return hipGraphLaunch(b->graphs[launches], s) == hipSuccess ? SIM_OK : SIM_EHIP;
+}
+
+// One call of at most kBatchMaxLaunches launches; steps[i] per slot.
+int run_chunk(sim_batch* b, const std::vector<int>& steps, hipStream_t s) {
+  const int k = b->tl.steps;
+  int launches = 0;
+  for (int i = 0; i < b->capacity; ++i)
+    if (steps[i] > 0) {
+      const int l = (steps[i] + k - 1) / k;
+      launches = l > launches ? l : launches;
+    }
+  if (launches == 0) return SIM_OK;
+  // the previous upload must have left the staging buffer
+  if (b->upload_pending && hipEventSynchronize(b->uploaded) != hipSuccess) return SIM_EHIP;
+  BatchSlot* hs = (BatchSlot*)(b->staging + b->L.slots);
+  BatchEntry* he = (BatchEntry*)(b->staging + b->L.entries);
+  int* hc = (int*)(b->staging + b->L.counts);
+  int* ht = (int*)(b->staging + b->L.totals);
+  memset(hs, 0, (size_t)b->capacity * sizeof(BatchSlot));
+  for (int i = 0; i < b->capacity; ++i) {
+    const HostSlot& x = b->slots[i];
+    if (!x.used || steps[i] <= 0) continue;
+    BatchSlot& d = hs[i];
+    d.S = x.S;
+    d.code[0] = x.user.code;
+    d.code[1] = x.shadow.code;
+    d.id[0] = x.user.id;
+    d.id[1] = x.shadow.id;
+    d.tau[0] = x.user.tau;
+    d.tau[1] = x.shadow.tau;
+    d.t0 = x.t;
+    d.steps = steps[i];
+    d.mode = x.mode;
+  }
+  for (int j = 0; j < launches; ++j) {
+    int n = 0, first = 0;
+    for (int i = 0; i < b->capacity; ++i) {
+      if (!b->slots[i].used || steps[i] <= j * k) continue;
+      he[(size_t)j * b->capacity + n] = BatchEntry{i, first};
+      first += b->slots[i].S.tiles_x * b->slots[i].S.tiles_y;
+      ++n;
+    }
+    hc[j] = n;
+    ht[j] = first;
+  }
+  if (hipMemcpyAsync(b->ws, b->staging, b->L.upload, hipMemcpyHostToDevice, s) != hipSuccess) return SIM_EHIP;
+  if (hipEventRecord(b->uploaded, s) != hipSuccess) return SIM_EHIP;
+  b->upload_pending = true;
+  const int rc = enqueue_sequence(b, launches, s);
+  if (rc) return rc;
+  for (int i = 0; i < b->capacity; ++i) {
+    HostSlot& x = b->slots[i];
+    if (!x.used || steps[i] <= 0) continue;
+    x.t += (uint64_t)steps[i];
+    x.stats_entries = x.S.tiles_x * x.S.tiles_y;
+  }
+  return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_batch_workspace_bytes(int32_t capacity, size_t* out) {
+  if (capacity < 1 || capacity > 65535 || !out) return SIM_EINVAL;
+  *out = batch_layout(capacity).total;
+  return SIM_OK;
+}
+
+int sim_batch_create(int32_t capacity, void* d_workspace, size_t workspace_bytes, sim_batch** out) {
+  if (!out || capacity < 1 || capacity > 65535) return SIM_EINVAL;
+  *out = nullptr;
+  const BatchLayout L = batch_layout(capacity);
+  if (!d_workspace || workspace_bytes < L.total) return SIM_ESCRATCH;
+  prepare_batch_kernels();
+  sim_batch* b = new (std::nothrow) sim_batch;
+  if (!b) return SIM_EINVAL;
+  b->capacity = capacity;
+  b->ws = (uint8_t*)d_workspace;
+  b->L = L;
+  b->staging = nullptr;
+  b->upload_pending = false;
+  b->tl = default_batch_tiling();
+  b->wgs_per_cu = 2;
+  b->use_graph = 1;
+  for (int i = 0; i <= kBatchMaxLaunches; ++i) b->graphs[i] = nullptr;
+  b->slots.resize(capacity);
+  if (hipHostMalloc((void**)&b->staging, L.upload, hipHostMallocDefault) != hipSuccess) {
+    delete b;
+    return SIM_EHIP;
+  }
+  if (hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess) {
+    (void)hipHostFree(b->staging);
+    delete b;
+    return SIM_EHIP;
+  }
+  if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipEventDestroy(b->uploaded);
+    (void)hipHostFree(b->staging);
+    delete b;
+    return SIM_EHIP;
+  }
+  *out = b;
+  return SIM_OK;
+}
+
+int sim_batch_add(sim_batch* b, const sim_params* p, int32_t mode, uint8_t* d_code, uint32_t* d_id, float* d_tau,
+                  void* d_scratch, size_t scratch_bytes, void* stream, int32_t* slot) {
+  if (!b || !slot) return SIM_EINVAL;
+  int e = check_params(p);
+  if (e) return e;
+  if (mode != kModeLem && mode != kModeAco) return SIM_EINVAL;
+  if (!d_code || !d_id) return SIM_EINVAL;
+  if (mode == kModeAco && !d_tau) return SIM_ENOTAU;
+  const ScratchLayout L = layout_of(p);
+  if (!d_scratch || scratch_bytes < L.total) return SIM_ESCRATCH;
+  int free_slot = -1;
+  for (int i = 0; i < b->capacity; ++i)
+    if (!b->slots[i].used) {
+      free_slot = i;
+      break;
+    }
+  if (free_slot < 0) return SIM_EFULL;
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* scratch = (uint8_t*)d_scratch;
+  e = validate_state(p, d_code, d_id, d_tau, scratch, L, s);
+  if (e) return e;
+  HostSlot hs;
+  hs.p = *p;
+  hs.mode = mode;
+  hs.user = Planes{d_code, d_id, d_tau};
+  hs.shadow = Planes{scratch + L.code2, (uint32_t*)(scratch + L.id2), d_tau ? (float*)(scratch + L.tau2) : nullptr};
+  hs.L = L;
+  hs.stats = (uint32_t*)(scratch + L.stats);
+  hs.totals = (unsigned long long*)(scratch + L.totals);
+  hs.t = p->step0;
+  if (!slot_geometry(b->tl, hs)) return SIM_EINVAL;
+  if (launch_count(d_code, p->W, p->H, p->cross_a, p->cross_b, hs.stats, &hs.stats_entries, s) != hipSuccess)
+    return SIM_EHIP;
+  hs.used = true;
+  b->slots[free_slot] = hs;
+  *slot = free_slot;
+  return SIM_OK;
+}
+
+int sim_batch_remove(sim_batch* b, int32_t slot) {
+  if (!b || slot < 0 || slot >= b->capacity || !b->slots[slot].used) return SIM_EINVAL;
+  b->slots[slot] = HostSlot();
+  return SIM_OK;
+}
+
+int sim_batch_step_slots(sim_batch* b, const int32_t* steps, int32_t n, void* stream) {
+  if (!b || !steps || n < 0 || n > b->capacity) return SIM_EINVAL;
+  std::vector<int> remaining(b->capacity, 0);
+  for (int i = 0; i < n; ++i) {
+    if (steps[i] < 0) return SIM_EINVAL;
+    if (steps[i] > 0 && !b->slots[i].used) return SIM_EINVAL;
+    remaining[i] = steps[i];
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int per_call = kBatchMaxLaunches * b->tl.steps;
+  for (;;) {
+    std::vector<int> now(b->capacity, 0);
+    bool any = false;
+    for (int i = 0; i < b->capacity; ++i) {
+      now[i] = remaining[i] < per_call ? remaining[i] : per_call;
+      remaining[i] -= now[i];
+      any = any || now[i] > 0;
+    }
+    if (!any) break;
+    const int rc = run_chunk(b, now, s);
+    if (rc) return rc;
+  }
+  return SIM_OK;
+}
+
+int sim_batch_step(sim_batch* b, int32_t nsteps, void* stream) {
+  if (!b || nsteps < 0) return SIM_EINVAL;
+  std::vector<int32_t> steps(b->capacity, 0);
+  for (int i = 0; i < b->capacity; ++i)
+    if (b->slots[i].used) steps[i] = nsteps;
+  return sim_batch_step_slots(b, steps.data(), b->capacity, stream);
+}
+
+int sim_batch_stats(sim_batch* b, int32_t slot, sim_stats_t* out, void* stream) {
+  if (!b || !out || slot < 0 || slot >= b->capacity || !b->slots[slot].used) return SIM_EINVAL;
+  const HostSlot& x = b->slots[slot];
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long v[kTileStatFields];
+  if (launch_reduce_counts(x.stats, x.stats_entries, x.totals, s) != hipSuccess) return SIM_EHIP;
+  if (hipMemcpyAsync(v, x.totals, sizeof(v), hipMemcpyDeviceToHost, s) != hipSuccess) return SIM_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return SIM_EHIP;
+  out->step = x.t;
+  out->agents_a = v[0];
+  out->agents_b = v[1];
+  out->crossed_a = v[2];
+  out->crossed_b = v[3];
+  out->moved_last = v[4];
+  return SIM_OK;
+}
+
+int sim_batch_set_tuning(sim_batch* b, int32_t nw, int32_t rows, int32_t steps_per_launch, int32_t threads,
+                         int32_t wgs_per_cu, int32_t use_graph) {
+  if (!b || wgs_per_cu < 1 || wgs_per_cu > 32) return SIM_EINVAL;
+  const Tiling tl{nw, rows, steps_per_launch, threads};
+  if (!tiling_valid(tl, true, max_dynamic_lds() - kBatchItemBytes)) return SIM_EINVAL;
+  for (int i = 0; i < b->capacity; ++i) {
+    if (!b->slots[i].used) continue;
+    HostSlot probe = b->slots[i];
+    if (!slot_geometry(tl, probe)) return SIM_EINVAL;
+  }
+  b->tl = tl;
+  for (int i = 0; i < b->capacity; ++i)
+    if (b->slots[i].used) slot_geometry(tl, b->slots[i]);
+  b->wgs_per_cu = wgs_per_cu;
+  b->use_graph = use_graph ? 1 : 0;
+  b->drop_graphs();
+  return SIM_OK;
+}
+
+int sim_batch_get_tuning(sim_batch* b, int32_t out[6]) {
+  if (!b || !out) return SIM_EINVAL;
+  out[0] = b->tl.nw;
+  out[1] = b->tl.rows;
+  out[2] = b->tl.steps;
+  out[3] = b->tl.threads;
+  out[4] = b->wgs_per_cu;
+  out[5] = b->use_graph;
+  return SIM_OK;
+}
+
+void sim_batch_destroy(sim_batch* b) {
+  if (!b) return;
+  if (b->upload_pending) (void)hipEventSynchronize(b->uploaded);
+  b->drop_graphs();
+  (void)hipStreamDestroy(b->capture);
+  (void)hipEventDestroy(b->uploaded);
+  (void)hipHostFree(b->staging);
+  delete b;
+}
+
+}  // extern "C"

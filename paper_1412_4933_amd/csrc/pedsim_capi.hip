@@ -14,25 +14,11 @@
 #include "pedsim.h"
 #include "pedsim_internal.hpp"
 
-using namespace pedsim;
+namespace pedsim {
 
-namespace {
-
-constexpr size_t kAlign = 256;
 size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-struct Planes {
-  uint8_t* code;
-  uint32_t* id;
-  float* tau;
-};
-
-struct ScratchLayout {
-  size_t code2, id2, tau2, stats, totals, total;
-  int stats_cap;
-};
-
-int count_entries(int W, int H) { return ((W + 63) / 64) * ((H + 3) / 4); }
+static int count_entries(int W, int H) { return ((W + 63) / 64) * ((H + 3) / 4); }
 
 ScratchLayout layout_of(const sim_params* p) {
   ScratchLayout L;
@@ -63,7 +49,65 @@ int check_params(const sim_params* p) {
 
 // eta^beta = D2^(-beta/2) for the squared distance D2 from a candidate to the
 // point two cells ahead (diagonal 2, lateral 5), rounded to float.
-float heuristic(double d2, int beta) { return (float)pow(d2, -0.5 * (double)beta); }
+static float heuristic(double d2, int beta) { return (float)pow(d2, -0.5 * (double)beta); }
+
+Scenario base_scenario(const sim_params* p) {
+  Scenario S;
+  memset(&S, 0, sizeof(S));
+  S.W = p->W;
+  S.H = p->H;
+  S.key0 = (uint32_t)p->seed;
+  S.key1 = (uint32_t)(p->seed >> 32);
+  const float rho = p->rho;
+  S.keep = 1.0f - rho;
+  S.dtau = p->dtau;
+  S.eta_diag = heuristic(2.0, p->beta);
+  S.eta_lat = heuristic(5.0, p->beta);
+  S.alpha = p->alpha;
+  S.cross_a = p->cross_a;
+  S.cross_b = p->cross_b;
+  return S;
+}
+
+void set_geometry(Scenario& S, const Tiling& tl) {
+  S.halo = 3 * tl.steps;
+  S.IX = 64 * tl.nw - 2 * S.halo;
+  S.IY = tl.rows - 2 * S.halo;
+  S.tiles_x = (S.W + S.IX - 1) / S.IX;
+  S.tiles_y = (S.H + S.IY - 1) / S.IY;
+}
+
+// Validate caller planes on the device (codes, id/code consistency, ids
+// exactly 1..N, pheromone finite and >= 0); synchronises the stream.
+int validate_state(const sim_params* p, const uint8_t* d_code, const uint32_t* d_id, const float* d_tau,
+                   uint8_t* scratch, const ScratchLayout& L, hipStream_t s) {
+  const size_t cells = (size_t)p->W * (size_t)p->H;
+  unsigned long long* counters = (unsigned long long*)(scratch + L.totals) + kTileStatFields;
+  unsigned long long host_counters[3];
+  if (hipMemsetAsync(counters, 0, 3 * sizeof(unsigned long long), s) != hipSuccess) return SIM_EHIP;
+  if (launch_validate(d_code, d_id, d_tau, cells, counters, s) != hipSuccess) return SIM_EHIP;
+  if (hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return SIM_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return SIM_EHIP;
+  if (host_counters[2]) return SIM_ESTATE;
+  const unsigned long long n = host_counters[0] + host_counters[1];
+  if (n > 0) {
+    uint32_t* bitmap = (uint32_t*)(scratch + L.id2);
+    if (hipMemsetAsync(bitmap, 0, (n + 31) / 32 * sizeof(uint32_t), s) != hipSuccess) return SIM_EHIP;
+    if (launch_validate_ids(d_id, cells, (uint32_t)n, bitmap, counters, s) != hipSuccess) return SIM_EHIP;
+    if (hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return SIM_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return SIM_EHIP;
+    if (host_counters[2]) return SIM_ESTATE;
+  }
+  return SIM_OK;
+}
+
+}  // namespace pedsim
+
+using namespace pedsim;
+
+namespace {
 
 // Default tiling by grid size (measured on MI355X): small grids want many
 // small tiles so every CU has one; large grids want tall regions and three
@@ -93,14 +137,6 @@ struct sim_handle {
 };
 
 namespace {
-
-void set_geometry(Scenario& S, const Tiling& tl) {
-  S.halo = 3 * tl.steps;
-  S.IX = 64 * tl.nw - 2 * S.halo;
-  S.IY = tl.rows - 2 * S.halo;
-  S.tiles_x = (S.W + S.IX - 1) / S.IX;
-  S.tiles_y = (S.H + S.IY - 1) / S.IY;
-}
 
 hipError_t copy_planes(const Planes& dst, const Planes& src, size_t cells, bool tau, hipStream_t s) {
   hipError_t e = hipMemcpyAsync(dst.code, src.code, cells, hipMemcpyDeviceToDevice, s);
@@ -227,27 +263,9 @@ int sim_create(const sim_params* p, uint8_t* d_code, uint32_t* d_id, float* d_ta
   hipStream_t s = (hipStream_t)stream;
   uint8_t* scratch = (uint8_t*)d_scratch;
   const size_t cells = (size_t)p->W * (size_t)p->H;
+  e = validate_state(p, d_code, d_id, d_tau, scratch, L, s);
+  if (e) return e;
   unsigned long long* totals = (unsigned long long*)(scratch + L.totals);
-  unsigned long long* counters = totals + kTileStatFields;  // 3 validation counters
-
-  // Validate the initial state on the device.
-  unsigned long long host_counters[3];
-  if (hipMemsetAsync(counters, 0, 3 * sizeof(unsigned long long), s) != hipSuccess) return SIM_EHIP;
-  if (launch_validate(d_code, d_id, d_tau, cells, counters, s) != hipSuccess) return SIM_EHIP;
-  if (hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s) != hipSuccess)
-    return SIM_EHIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return SIM_EHIP;
-  if (host_counters[2]) return SIM_ESTATE;
-  const unsigned long long n = host_counters[0] + host_counters[1];
-  if (n > 0) {
-    uint32_t* bitmap = (uint32_t*)(scratch + L.id2);
-    if (hipMemsetAsync(bitmap, 0, (n + 31) / 32 * sizeof(uint32_t), s) != hipSuccess) return SIM_EHIP;
-    if (launch_validate_ids(d_id, cells, (uint32_t)n, bitmap, counters, s) != hipSuccess) return SIM_EHIP;
-    if (hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s) != hipSuccess)
-      return SIM_EHIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return SIM_EHIP;
-    if (host_counters[2]) return SIM_ESTATE;
-  }
 
   sim_handle* h = new (std::nothrow) sim_handle;
   if (!h) return SIM_EINVAL;
@@ -258,20 +276,7 @@ int sim_create(const sim_params* p, uint8_t* d_code, uint32_t* d_id, float* d_ta
   h->stats_cap = L.stats_cap;
   h->totals = totals;
   h->t = p->step0;
-  Scenario& S = h->base;
-  memset(&S, 0, sizeof(S));
-  S.W = p->W;
-  S.H = p->H;
-  S.key0 = (uint32_t)p->seed;
-  S.key1 = (uint32_t)(p->seed >> 32);
-  const float rho = p->rho;
-  S.keep = 1.0f - rho;
-  S.dtau = p->dtau;
-  S.eta_diag = heuristic(2.0, p->beta);
-  S.eta_lat = heuristic(5.0, p->beta);
-  S.alpha = p->alpha;
-  S.cross_a = p->cross_a;
-  S.cross_b = p->cross_b;
+  h->base = base_scenario(p);
   h->tiling[kModeLem] = default_tiling(false, cells);
   h->tiling[kModeAco] = default_tiling(true, cells);
   if (launch_count(d_code, p->W, p->H, p->cross_a, p->cross_b, h->stats, &h->stats_entries, s) != hipSuccess) {

@@ -48,3 +48,80 @@ hipError_t launch_validate_ids(const uint32_t* id, size_t cells, uint32_t n, uin
 int max_dynamic_lds();
 
 }  // namespace pedsim
+
+#include "pedsim.h"
+
+namespace pedsim {
+
+// Host-side helpers shared by the single-scenario and batch C ABIs.
+constexpr size_t kAlign = 256;
+size_t round_up(size_t v);
+
+struct Planes {
+  uint8_t* code;
+  uint32_t* id;
+  float* tau;
+};
+
+// Per-scenario scratch: shadow planes (code, id, both pheromone planes),
+// per-tile counters, totals and validation counters.
+struct ScratchLayout {
+  size_t code2, id2, tau2, stats, totals, total;
+  int stats_cap;
+};
+
+ScratchLayout layout_of(const sim_params* p);
+int check_params(const sim_params* p);
+Scenario base_scenario(const sim_params* p);
+void set_geometry(Scenario& S, const Tiling& tl);
+int validate_state(const sim_params* p, const uint8_t* d_code, const uint32_t* d_id, const float* d_tau,
+                   uint8_t* scratch, const ScratchLayout& L, hipStream_t s);
+
+}  // namespace pedsim
+
+namespace pedsim {
+
+// ---------------------------------------------------------------------------
+// Batched form: many independent scenarios advanced together.
+// ---------------------------------------------------------------------------
+
+// One scenario of a batch as the device sees it during one call.
+struct BatchSlot {
+  Scenario S;         // parameters and tile geometry; plane pointers set per launch
+  uint8_t* code[2];   // [0] caller planes, [1] shadow planes in the slot's scratch
+  uint32_t* id[2];
+  float* tau[2];
+  uint64_t t0;        // index of the slot's first step in this call
+  int steps;          // steps the slot runs in this call (0: idle)
+  int mode;           // kModeLem or kModeAco
+};
+
+// Launch j of a call processes, in order, the tiles of every slot with
+// steps > j * k: entries[j * capacity + e] = {slot, index of its first tile
+// among the launch's work items}.
+struct BatchEntry {
+  int slot;
+  int first;
+};
+
+struct BatchPlan {
+  const BatchSlot* slots;
+  const BatchEntry* entries;  // [launch][capacity]
+  const int* counts;          // [launch] number of entries
+  const int* totals;          // [launch] number of work items (tiles)
+  unsigned* counters;         // [launch] work-claim counters
+  int capacity;
+  int k;                      // steps per launch
+  int rows;                   // region rows
+};
+
+constexpr int kBatchMaxLaunches = 128;  // launches per captured graph
+constexpr int kBatchItemBytes = 16;     // LDS the batch kernel needs beyond the tile layout
+
+hipError_t launch_batch_reset(const BatchPlan& P, int launches, hipStream_t s);
+hipError_t launch_batch(const BatchPlan& P, const Tiling& tl, int j, int grid, hipStream_t s);
+hipError_t launch_batch_copyback(const BatchPlan& P, int capacity, hipStream_t s);
+int device_cu_count();
+void prepare_batch_kernels();  // sets the batch kernels' LDS limit once (outside any capture)
+
+}  // namespace pedsim

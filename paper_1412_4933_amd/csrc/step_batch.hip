@@ -1,0 +1,120 @@
+// Batched form: one persistent kernel launch advances every active scenario
+// of a batch by up to k steps. Workgroups claim (scenario, tile) work items
+// from a per-launch counter; each item runs the tile engine with the
+// scenario's own parameters and mode (LEM or ACO), so scenarios of any size
+// and mode share the launch. A call is a fixed sequence (counter reset, one
+// launch per k steps, copy back of scenarios whose state ended in their
+// shadow planes) that the host captures once in a hipGraph and replays with
+// new tables.
+#include "pedsim_internal.hpp"
+
+namespace pedsim {
+
+template <int NW>
+__global__ __launch_bounds__(1024) void batch_kernel(BatchPlan P, int j) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  // the claimed item is passed through the word after the tile's LDS layout
+  int& s_item = *(int*)(smem + Layout<NW>{P.rows, true}.bytes());
+  const int count = P.counts[j];
+  const int total = P.totals[j];
+  const BatchEntry* E = P.entries + (size_t)j * P.capacity;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(&P.counters[j], 1u);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (item >= total) break;
+    int lo = 0, hi = count - 1;  // last entry whose first item is <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (E[mid].first <= item) lo = mid; else hi = mid - 1;
+    }
+    const BatchSlot& B = P.slots[E[lo].slot];
+    Scenario S = B.S;
+    const int par = j & 1;
+    S.code_in = B.code[par];
+    S.id_in = B.id[par];
+    S.tau_in = B.tau[par];
+    S.code_out = B.code[par ^ 1];
+    S.id_out = B.id[par ^ 1];
+    S.tau_out = B.tau[par ^ 1];
+    const int done = j * P.k;
+    const int steps = B.steps - done < P.k ? B.steps - done : P.k;
+    const bool last = done + steps == B.steps;
+    const int tile = item - E[lo].first;
+    const int tx = tile % S.tiles_x, ty = tile / S.tiles_x;
+    if (B.mode == kModeAco)
+      advance_tile<NW, kModeAco>(S, smem, P.rows, tx, ty, tile, B.t0 + (uint64_t)done, steps, last);
+    else
+      advance_tile<NW, kModeLem>(S, smem, P.rows, tx, ty, tile, B.t0 + (uint64_t)done, steps, last);
+  }
+}
+
+__global__ void batch_reset_kernel(unsigned* counters, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) counters[i] = 0u;
+}
+
+// A slot that ran an odd number of launches has its state in the shadow
+// planes: copy it back (blockIdx.y = slot).
+__global__ __launch_bounds__(256) void batch_copyback_kernel(BatchPlan P) {
+  const BatchSlot& B = P.slots[blockIdx.y];
+  if (B.steps <= 0) return;
+  const int launches = (B.steps + P.k - 1) / P.k;
+  if ((launches & 1) == 0) return;
+  const size_t cells = (size_t)B.S.W * (size_t)B.S.H;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells; i += stride) {
+    B.code[0][i] = B.code[1][i];
+    B.id[0][i] = B.id[1][i];
+    if (B.mode == kModeAco) {
+      B.tau[0][i] = B.tau[1][i];
+      B.tau[0][cells + i] = B.tau[1][cells + i];
+    }
+  }
+}
+
+hipError_t launch_batch_reset(const BatchPlan& P, int launches, hipStream_t s) {
+  batch_reset_kernel<<<1, 256, 0, s>>>(P.counters, launches);
+  return hipGetLastError();
+}
+
+void prepare_batch_kernels() {
+  static bool done = false;
+  if (done) return;
+  (void)hipFuncSetAttribute((const void*)batch_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            max_dynamic_lds());
+  (void)hipFuncSetAttribute((const void*)batch_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            max_dynamic_lds());
+  (void)hipGetLastError();  // an unsupported attribute value must not linger as the last error
+  done = true;
+}
+
+template <int NW>
+static hipError_t launch_batch_nw(const BatchPlan& P, const Tiling& tl, int j, int grid, hipStream_t s) {
+  const size_t lds = Layout<NW>{tl.rows, true}.bytes() + kBatchItemBytes;
+  batch_kernel<NW><<<grid, tl.threads, lds, s>>>(P, j);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchPlan& P, const Tiling& tl, int j, int grid, hipStream_t s) {
+  return tl.nw == 1 ? launch_batch_nw<1>(P, tl, j, grid, s) : launch_batch_nw<2>(P, tl, j, grid, s);
+}
+
+hipError_t launch_batch_copyback(const BatchPlan& P, int capacity, hipStream_t s) {
+  batch_copyback_kernel<<<dim3(64, capacity), 256, 0, s>>>(P);
+  return hipGetLastError();
+}
+
+int device_cu_count() {
+  static int cached = -1;
+  if (cached < 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+      v = 256;
+    cached = v;
+  }
+  return cached;
+}
+
+}  // namespace pedsim

@@ -52,6 +52,7 @@ static hipError_t launch_one(const Scenario& S, const Tiling& tl, uint64_t t0, i
   if (!attr_done) {
     (void)hipFuncSetAttribute((const void*)tile_kernel<NW, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               max_dynamic_lds());
+    (void)hipGetLastError();  // an unsupported attribute value must not linger as the last error
     attr_done = true;
   }
   const int ntiles = S.tiles_x * S.tiles_y;

@@ -83,21 +83,22 @@ def lib() -> ctypes.CDLL:
 
 
 def _bind_batch(L):
-    if not hasattr(L, "sim_batch_create"):
-        return
     vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
     P = ctypes.POINTER
-    L.sim_batch_create.argtypes = [i32, P(vp)]
+    L.sim_batch_workspace_bytes.argtypes = [i32, P(sz)]
+    L.sim_batch_create.argtypes = [i32, vp, sz, P(vp)]
     L.sim_batch_add.argtypes = [vp, P(SimParams), i32, vp, vp, vp, vp, sz, vp, P(i32)]
     L.sim_batch_remove.argtypes = [vp, i32]
     L.sim_batch_step.argtypes = [vp, i32, vp]
     L.sim_batch_step_slots.argtypes = [vp, P(i32), i32, vp]
     L.sim_batch_stats.argtypes = [vp, i32, P(SimStats), vp]
+    L.sim_batch_set_tuning.argtypes = [vp, i32, i32, i32, i32, i32, i32]
+    L.sim_batch_get_tuning.argtypes = [vp, P(i32)]
     L.sim_batch_destroy.argtypes = [vp]
     L.sim_batch_destroy.restype = None
-    L.sim_batch_set_tuning.argtypes = [vp, i32, i32]
-    for name in ("sim_batch_create", "sim_batch_add", "sim_batch_remove", "sim_batch_step",
-                 "sim_batch_step_slots", "sim_batch_stats", "sim_batch_set_tuning"):
+    for name in ("sim_batch_workspace_bytes", "sim_batch_create", "sim_batch_add", "sim_batch_remove",
+                 "sim_batch_step", "sim_batch_step_slots", "sim_batch_stats", "sim_batch_set_tuning",
+                 "sim_batch_get_tuning"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -192,6 +193,64 @@ def sim_destroy(h) -> None:
         lib().sim_destroy(h)
 
 
+def sim_batch_workspace_bytes(capacity: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().sim_batch_workspace_bytes(int(capacity), ctypes.byref(out)), "sim_batch_workspace_bytes")
+    return int(out.value)
+
+
+def sim_batch_create(capacity: int, workspace, workspace_bytes: int):
+    b = ctypes.c_void_p()
+    _check(lib().sim_batch_create(int(capacity), _ptr(workspace), int(workspace_bytes), ctypes.byref(b)),
+           "sim_batch_create")
+    return b
+
+
+def sim_batch_add(b, params: SimParams, mode: int, code, ids, tau, scratch, scratch_bytes: int,
+                  stream=None) -> int:
+    slot = ctypes.c_int32()
+    _check(lib().sim_batch_add(b, ctypes.byref(params), int(mode), _ptr(code), _ptr(ids), _ptr(tau),
+                               _ptr(scratch), int(scratch_bytes), _stream(stream), ctypes.byref(slot)),
+           "sim_batch_add")
+    return int(slot.value)
+
+
+def sim_batch_remove(b, slot: int) -> None:
+    _check(lib().sim_batch_remove(b, int(slot)), "sim_batch_remove")
+
+
+def sim_batch_step(b, nsteps: int, stream=None) -> None:
+    _check(lib().sim_batch_step(b, int(nsteps), _stream(stream)), "sim_batch_step")
+
+
+def sim_batch_step_slots(b, steps, stream=None) -> None:
+    arr = (ctypes.c_int32 * len(steps))(*[int(v) for v in steps])
+    _check(lib().sim_batch_step_slots(b, arr, len(steps), _stream(stream)), "sim_batch_step_slots")
+
+
+def sim_batch_stats(b, slot: int, stream=None) -> dict:
+    s = SimStats()
+    _check(lib().sim_batch_stats(b, int(slot), ctypes.byref(s), _stream(stream)), "sim_batch_stats")
+    return s.as_dict()
+
+
+def sim_batch_set_tuning(b, nw: int, rows: int, steps_per_launch: int, threads: int, wgs_per_cu: int,
+                         use_graph: int = 1) -> None:
+    _check(lib().sim_batch_set_tuning(b, int(nw), int(rows), int(steps_per_launch), int(threads),
+                                      int(wgs_per_cu), int(use_graph)), "sim_batch_set_tuning")
+
+
+def sim_batch_get_tuning(b):
+    out = (ctypes.c_int32 * 6)()
+    _check(lib().sim_batch_get_tuning(b, out), "sim_batch_get_tuning")
+    return tuple(int(v) for v in out)
+
+
+def sim_batch_destroy(b) -> None:
+    if b:
+        lib().sim_batch_destroy(b)
+
+
 # --- convenience: a scenario resident in torch device tensors -------------------
 
 def params_of(s, step0: int = 0) -> SimParams:
@@ -252,6 +311,98 @@ class Sim:
         if self.h:
             sim_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Resident:
+    """Device planes and scratch of one scenario (torch tensors)."""
+
+    def __init__(self, scenario, device, step0: int = 0):
+        import torch
+        self.scenario = scenario
+        self.params = params_of(scenario, step0)
+        self.code = torch.from_numpy(np.ascontiguousarray(scenario.code)).to(device)
+        self.ids = torch.from_numpy(np.ascontiguousarray(scenario.ids).view(np.int32)).to(device)
+        self.tau = None
+        if scenario.tau is not None:
+            self.tau = torch.from_numpy(np.ascontiguousarray(scenario.tau)).to(device)
+        self.scratch_bytes = sim_scratch_bytes(self.params)
+        self.scratch = torch.empty(self.scratch_bytes, dtype=torch.uint8, device=device)
+
+    def nbytes(self) -> int:
+        n = self.code.numel() + 4 * self.ids.numel() + self.scratch_bytes
+        return n + (4 * self.tau.numel() if self.tau is not None else 0)
+
+    def state(self):
+        code = self.code.cpu().numpy()
+        ids = self.ids.cpu().numpy().view(np.uint32)
+        tau = None if self.tau is None else self.tau.cpu().numpy()
+        return code, ids, tau
+
+
+class Batch:
+    """Many scenarios resident on one GPU, advanced together by the batched
+    kernel. Device memory comes from torch; slots are the library's."""
+
+    def __init__(self, capacity: int, device: str = "cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream
+        self.capacity = capacity
+        nbytes = sim_batch_workspace_bytes(capacity)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.b = sim_batch_create(capacity, self.workspace, nbytes)
+        self.members = {}
+
+    def add(self, scenario, mode: Optional[int] = None, step0: int = 0) -> int:
+        mode = scenario.mode if mode is None else mode
+        res = _Resident(scenario, self.device, step0)
+        self.torch.cuda.synchronize(self.device)
+        slot = sim_batch_add(self.b, res.params, mode, res.code, res.ids, res.tau, res.scratch,
+                             res.scratch_bytes, self.stream)
+        self.members[slot] = res
+        return slot
+
+    def remove(self, slot: int) -> None:
+        sim_batch_remove(self.b, slot)
+        self.members.pop(slot, None)
+
+    def step(self, nsteps: int) -> None:
+        sim_batch_step(self.b, nsteps, self.stream)
+
+    def step_slots(self, steps) -> None:
+        """steps: list indexed by slot, or {slot: steps}."""
+        if isinstance(steps, dict):
+            arr = [0] * self.capacity
+            for k, v in steps.items():
+                arr[k] = v
+            steps = arr
+        sim_batch_step_slots(self.b, steps, self.stream)
+
+    def stats(self, slot: int) -> dict:
+        return sim_batch_stats(self.b, slot, self.stream)
+
+    def state(self, slot: int):
+        s = self.stream if self.stream is not None else self.torch.cuda.current_stream(self.device)
+        s.synchronize()
+        return self.members[slot].state()
+
+    def set_tuning(self, nw, rows, steps_per_launch, threads, wgs_per_cu, use_graph=1) -> None:
+        sim_batch_set_tuning(self.b, nw, rows, steps_per_launch, threads, wgs_per_cu, use_graph)
+
+    def tuning(self):
+        return sim_batch_get_tuning(self.b)
+
+    def close(self) -> None:
+        if self.b:
+            sim_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:
