@@ -24,10 +24,16 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 WORKLOADS = {
     "aco_1024x512": ("aco_1024x512", "ACO 1024x512, 50,000 agents per group (100K), 2,000 steps"),
+    "batched_256": ("batched_256", "256 independent scenarios, widths log-uniform 64-2048, H=W/2, "
+                    "500-100K agents, half LEM half ACO, seeds 0..255, in one batch"),
+    "served": ("served_requests", "Poisson stream of scenarios drawn like the batch, 200-2000 steps each, "
+               "continuous batching under an HBM budget"),
     "lem_200x100": ("lem_200x100", "LEM 200x100, 1,000 agents per group, 500 steps"),
     "stress_aco_4096x2048": ("stress_4096x2048", "ACO 4096x2048, 5% obstacles, 1M agents"),
     "stress_lem_4096x2048": ("stress_4096x2048", "LEM 4096x2048, 5% obstacles, 1M agents"),
 }
+# workloads run by the single-scenario path
+PLAIN = ("aco_1024x512", "lem_200x100", "stress_aco_4096x2048", "stress_lem_4096x2048")
 
 
 def log(*a):
@@ -89,6 +95,83 @@ def cpu_baseline(workload: str, budget_s: float):
                       f"plain C oracle, one thread, {dt:.1f} s"}
 
 
+def run_batched(args):
+    """All 256 scenarios advanced together vs the same scenarios one after
+    another through the plain path; K steps each."""
+    import torch
+    from paper_1412_4933_amd import autotune, pedsim, scenarios
+    K = args.steps if args.steps is not None else 1000
+    scns = scenarios.batched_256(steps=K)
+    agents = sum(s.agents for s in scns)
+    tuning = None
+    if args.autotune:
+        log("autotuning the batch ...")
+        tuning, timings = autotune.tune_batch(scns, steps=20)
+        log("autotune:", [(round(t * 1e3, 2), tu) for t, tu in timings[:5]])
+    batch = pedsim.Batch(len(scns))
+    if tuning is not None:
+        batch.set_tuning(*tuning, 1)
+    for sc in scns:
+        batch.add(sc)
+    log(f"batch of {len(scns)} scenarios, {agents} agents, tuning {batch.tuning()}")
+    batch.step(args.warmup)  # also instantiates the captured launch sequences
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(K)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    batch.close()
+    value = agents * K / wall
+    log(f"batched: {K} steps in {wall * 1e3:.1f} ms -> {value:.4g} agent-steps/s")
+    # back-to-back plain launches of the same scenarios (step calls only)
+    plain = 0.0
+    for sc in scns:
+        sim = pedsim.Sim(sc)
+        sim.step(args.warmup, sc.mode)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sim.step(K, sc.mode)
+        torch.cuda.synchronize()
+        plain += time.perf_counter() - t1
+        sim.close()
+    log(f"back-to-back plain: {plain * 1e3:.1f} ms -> {agents * K / plain:.4g} agent-steps/s")
+    line = {
+        "metric": "agent-steps/s (batched, 256 scenarios)", "value": value, "unit": "agent-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": wall * 1e3 / K,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+u32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["batched_256"][1], "scenarios": len(scns), "agents": agents,
+                   "tuning": list(batch_tuning_or(tuning))},
+        "back_to_back_plain": {"value": agents * K / plain, "wall_s": plain},
+        "speedup_vs_back_to_back": plain / wall,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def batch_tuning_or(tuning):
+    return tuning if tuning is not None else ("default",)
+
+
+def served_run(n_requests: int, rate: float, budget: int, quantum: int, seed: int = 1):
+    """Continuous batching of a Poisson request stream, and the same requests
+    back to back through the plain path."""
+    from paper_1412_4933_amd import scenarios, serve
+    specs = scenarios.served_requests(n_requests, rng_seed=seed)
+    reqs = serve.poisson_requests(specs, rate=rate, seed=seed)
+    srv = serve.Server(capacity=256, budget_bytes=budget, quantum=quantum)
+    t0 = time.perf_counter()
+    results = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    srv.close()
+    summary = serve.summarize(results, wall)
+    b2b = serve.run_back_to_back(reqs)
+    summary.update({"rate_per_s": rate, "budget_bytes": budget, "quantum": quantum,
+                    "back_to_back_agent_steps_per_s": b2b["agent_steps_per_s"],
+                    "back_to_back_wall_s": b2b["wall_s"],
+                    "speedup_vs_back_to_back": b2b["wall_s"] / wall})
+    return summary
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,11 +180,26 @@ def main():
     ap.add_argument("--workload", default="aco_1024x512", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--autotune", action="store_true", help="autotune the batch launch shape first")
+    ap.add_argument("--requests", type=int, default=64, help="requests in the served run")
+    ap.add_argument("--rate", type=float, default=400.0, help="request arrival rate (1/s)")
+    ap.add_argument("--budget-gib", type=float, default=2.0, help="HBM budget for resident scenarios")
+    ap.add_argument("--quantum", type=int, default=100, help="steps per serving quantum")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served run of the default line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched_256":
+        return run_batched(args)
+    if args.workload == "served":
+        summary = served_run(args.requests, args.rate, int(args.budget_gib * (1 << 30)), args.quantum)
+        log("served:", summary)
+        print(json.dumps({"metric": "batched p50/p99 scenario latency (served)", "value": summary["p99_latency_s"],
+                          "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+                          "config": {"workload": WORKLOADS["served"][1]}, "served": summary}), flush=True)
+        return
 
     import torch
     from paper_1412_4933_amd import pedsim
@@ -157,6 +255,12 @@ def main():
                 "kernels": {k: {"avg_us": round(v[0] / v[1] * 1e3, 3) if v[1] else 0.0,
                                 "launches": v[1]} for k, v in per_kernel.items()}}
 
+    served = None
+    if not args.no_serve:
+        log(f"served run: {args.requests} requests at {args.rate}/s ...")
+        served = served_run(args.requests, args.rate, int(args.budget_gib * (1 << 30)), args.quantum)
+        log("served:", served)
+
     cpu = None
     if not args.no_cpu:
         log("timing the CPU oracle ...")
@@ -174,6 +278,7 @@ def main():
                    "agents": agents, "mode": "ACO" if mode == 1 else "LEM", "seed": scn.seed},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "served": served,
     }
     print(json.dumps(line), flush=True)
 

@@ -208,6 +208,11 @@ void sim_batch_destroy(sim_batch* b);
 /* Static text for a SIM_* code. */
 const char* sim_strerror(int code);
 
+/* Details of the most recent SIM_EHIP on the calling thread: the failing HIP
+ * call, its error string and code ("" if none yet). Valid until the next
+ * failing call on the same thread. */
+const char* sim_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -117,23 +117,27 @@ int enqueue_sequence(sim_batch* b, int launches, hipStream_t s) {
     if (e == hipSuccess) e = launch_batch_copyback(P, b->capacity, on);
     return e;
   };
-  if (!b->use_graph) return issue(s) == hipSuccess ? SIM_OK : SIM_EHIP;
+  if (!b->use_graph) {
+    PEDSIM_HIP(issue(s));
+    return SIM_OK;
+  }
   if (!b->graphs[launches]) {
     hipGraph_t g = nullptr;
-    if (hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return SIM_EHIP;
+    PEDSIM_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
     const hipError_t e = issue(b->capture);
     const hipError_t e2 = hipStreamEndCapture(b->capture, &g);
     if (e != hipSuccess || e2 != hipSuccess || !g) {
       if (g) (void)hipGraphDestroy(g);
-      return SIM_EHIP;
+      return hip_fail(e != hipSuccess ? e : e2, "capture of the batch launch sequence", __LINE__);
     }
     hipGraphExec_t exec = nullptr;
     const hipError_t e3 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (e3 != hipSuccess) return SIM_EHIP;
+    PEDSIM_HIP(e3);
     b->graphs[launches] = exec;
   }
-  return hipGraphLaunch(b->graphs[launches], s) == hipSuccess ? SIM_OK : SIM_EHIP;
+  PEDSIM_HIP(hipGraphLaunch(b->graphs[launches], s));
+  return SIM_OK;
 }
 
 // One call of at most kBatchMaxLaunches launches; steps[i] per slot.
@@ -147,7 +151,7 @@ int run_chunk(sim_batch* b, const std::vector<int>& steps, hipStream_t s) {
     }
   if (launches == 0) return SIM_OK;
   // the previous upload must have left the staging buffer
-  if (b->upload_pending && hipEventSynchronize(b->uploaded) != hipSuccess) return SIM_EHIP;
+  if (b->upload_pending) PEDSIM_HIP(hipEventSynchronize(b->uploaded));
   BatchSlot* hs = (BatchSlot*)(b->staging + b->L.slots);
   BatchEntry* he = (BatchEntry*)(b->staging + b->L.entries);
   int* hc = (int*)(b->staging + b->L.counts);
@@ -179,8 +183,8 @@ int run_chunk(sim_batch* b, const std::vector<int>& steps, hipStream_t s) {
     hc[j] = n;
     ht[j] = first;
   }
-  if (hipMemcpyAsync(b->ws, b->staging, b->L.upload, hipMemcpyHostToDevice, s) != hipSuccess) return SIM_EHIP;
-  if (hipEventRecord(b->uploaded, s) != hipSuccess) return SIM_EHIP;
+  PEDSIM_HIP(hipMemcpyAsync(b->ws, b->staging, b->L.upload, hipMemcpyHostToDevice, s));
+  PEDSIM_HIP(hipEventRecord(b->uploaded, s));
   b->upload_pending = true;
   const int rc = enqueue_sequence(b, launches, s);
   if (rc) return rc;
@@ -221,20 +225,23 @@ int sim_batch_create(int32_t capacity, void* d_workspace, size_t workspace_bytes
   b->use_graph = 1;
   for (int i = 0; i <= kBatchMaxLaunches; ++i) b->graphs[i] = nullptr;
   b->slots.resize(capacity);
-  if (hipHostMalloc((void**)&b->staging, L.upload, hipHostMallocDefault) != hipSuccess) {
+  hipError_t e = hipHostMalloc((void**)&b->staging, L.upload, hipHostMallocDefault);
+  if (e != hipSuccess) {
     delete b;
-    return SIM_EHIP;
+    return hip_fail(e, "hipHostMalloc(staging)", __LINE__);
   }
-  if (hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess) {
+  e = hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming);
+  if (e != hipSuccess) {
     (void)hipHostFree(b->staging);
     delete b;
-    return SIM_EHIP;
+    return hip_fail(e, "hipEventCreateWithFlags", __LINE__);
   }
-  if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess) {
+  e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+  if (e != hipSuccess) {
     (void)hipEventDestroy(b->uploaded);
     (void)hipHostFree(b->staging);
     delete b;
-    return SIM_EHIP;
+    return hip_fail(e, "hipStreamCreateWithFlags", __LINE__);
   }
   *out = b;
   return SIM_OK;
@@ -271,8 +278,7 @@ int sim_batch_add(sim_batch* b, const sim_params* p, int32_t mode, uint8_t* d_co
   hs.totals = (unsigned long long*)(scratch + L.totals);
   hs.t = p->step0;
   if (!slot_geometry(b->tl, hs)) return SIM_EINVAL;
-  if (launch_count(d_code, p->W, p->H, p->cross_a, p->cross_b, hs.stats, &hs.stats_entries, s) != hipSuccess)
-    return SIM_EHIP;
+  PEDSIM_HIP(launch_count(d_code, p->W, p->H, p->cross_a, p->cross_b, hs.stats, &hs.stats_entries, s));
   hs.used = true;
   b->slots[free_slot] = hs;
   *slot = free_slot;
@@ -323,9 +329,9 @@ int sim_batch_stats(sim_batch* b, int32_t slot, sim_stats_t* out, void* stream) 
   const HostSlot& x = b->slots[slot];
   hipStream_t s = (hipStream_t)stream;
   unsigned long long v[kTileStatFields];
-  if (launch_reduce_counts(x.stats, x.stats_entries, x.totals, s) != hipSuccess) return SIM_EHIP;
-  if (hipMemcpyAsync(v, x.totals, sizeof(v), hipMemcpyDeviceToHost, s) != hipSuccess) return SIM_EHIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return SIM_EHIP;
+  PEDSIM_HIP(launch_reduce_counts(x.stats, x.stats_entries, x.totals, s));
+  PEDSIM_HIP(hipMemcpyAsync(v, x.totals, sizeof(v), hipMemcpyDeviceToHost, s));
+  PEDSIM_HIP(hipStreamSynchronize(s));
   out->step = x.t;
   out->agents_a = v[0];
   out->agents_b = v[1];

@@ -6,6 +6,7 @@
 // tile's halo is its neighbours' interior); the call ends with the state back
 // in the caller's planes.
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -15,6 +16,14 @@
 #include "pedsim_internal.hpp"
 
 namespace pedsim {
+
+static thread_local char g_last_error[256] = "";
+
+int hip_fail(hipError_t e, const char* what, int line) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s (%d) from %.150s at line %d", hipGetErrorString(e), (int)e,
+           what, line);
+  return SIM_EHIP;
+}
 
 size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -84,20 +93,18 @@ int validate_state(const sim_params* p, const uint8_t* d_code, const uint32_t* d
   const size_t cells = (size_t)p->W * (size_t)p->H;
   unsigned long long* counters = (unsigned long long*)(scratch + L.totals) + kTileStatFields;
   unsigned long long host_counters[3];
-  if (hipMemsetAsync(counters, 0, 3 * sizeof(unsigned long long), s) != hipSuccess) return SIM_EHIP;
-  if (launch_validate(d_code, d_id, d_tau, cells, counters, s) != hipSuccess) return SIM_EHIP;
-  if (hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s) != hipSuccess)
-    return SIM_EHIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return SIM_EHIP;
+  PEDSIM_HIP(hipMemsetAsync(counters, 0, 3 * sizeof(unsigned long long), s));
+  PEDSIM_HIP(launch_validate(d_code, d_id, d_tau, cells, counters, s));
+  PEDSIM_HIP(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s));
+  PEDSIM_HIP(hipStreamSynchronize(s));
   if (host_counters[2]) return SIM_ESTATE;
   const unsigned long long n = host_counters[0] + host_counters[1];
   if (n > 0) {
     uint32_t* bitmap = (uint32_t*)(scratch + L.id2);
-    if (hipMemsetAsync(bitmap, 0, (n + 31) / 32 * sizeof(uint32_t), s) != hipSuccess) return SIM_EHIP;
-    if (launch_validate_ids(d_id, cells, (uint32_t)n, bitmap, counters, s) != hipSuccess) return SIM_EHIP;
-    if (hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s) != hipSuccess)
-      return SIM_EHIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return SIM_EHIP;
+    PEDSIM_HIP(hipMemsetAsync(bitmap, 0, (n + 31) / 32 * sizeof(uint32_t), s));
+    PEDSIM_HIP(launch_validate_ids(d_id, cells, (uint32_t)n, bitmap, counters, s));
+    PEDSIM_HIP(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s));
+    PEDSIM_HIP(hipStreamSynchronize(s));
     if (host_counters[2]) return SIM_ESTATE;
   }
   return SIM_OK;
@@ -195,10 +202,10 @@ int run_steps(sim_handle* h, int mode, int32_t nsteps, hipStream_t s, hipEvent_t
       S.tile_stats = h->stats;
       const bool last = done + chunk[j] == nsteps;
       if (ev) (void)hipEventRecord(ev[0], s);
-      if (launch_tiles(S, tl, mode, h->t, chunk[j], last, s) != hipSuccess) return SIM_EHIP;
+      PEDSIM_HIP(launch_tiles(S, tl, mode, h->t, chunk[j], last, s));
       if (ev) {
         (void)hipEventRecord(ev[1], s);
-        if (hipEventSynchronize(ev[1]) != hipSuccess) return SIM_EHIP;
+        PEDSIM_HIP(hipEventSynchronize(ev[1]));
         float f = 0.0f;
         (void)hipEventElapsedTime(&f, ev[0], ev[1]);
         ms[0] += f;
@@ -213,10 +220,10 @@ int run_steps(sim_handle* h, int mode, int32_t nsteps, hipStream_t s, hipEvent_t
   }
   if (src.code != h->user.code) {  // odd number of launches: state is in the shadow planes
     if (ev) (void)hipEventRecord(ev[0], s);
-    if (copy_planes(h->user, src, cells, aco, s) != hipSuccess) return SIM_EHIP;
+    PEDSIM_HIP(copy_planes(h->user, src, cells, aco, s));
     if (ev) {
       (void)hipEventRecord(ev[1], s);
-      if (hipEventSynchronize(ev[1]) != hipSuccess) return SIM_EHIP;
+      PEDSIM_HIP(hipEventSynchronize(ev[1]));
       float f = 0.0f;
       (void)hipEventElapsedTime(&f, ev[0], ev[1]);
       ms[1] += f;
@@ -279,9 +286,10 @@ int sim_create(const sim_params* p, uint8_t* d_code, uint32_t* d_id, float* d_ta
   h->base = base_scenario(p);
   h->tiling[kModeLem] = default_tiling(false, cells);
   h->tiling[kModeAco] = default_tiling(true, cells);
-  if (launch_count(d_code, p->W, p->H, p->cross_a, p->cross_b, h->stats, &h->stats_entries, s) != hipSuccess) {
+  const hipError_t e2 = launch_count(d_code, p->W, p->H, p->cross_a, p->cross_b, h->stats, &h->stats_entries, s);
+  if (e2 != hipSuccess) {
     delete h;
-    return SIM_EHIP;
+    return hip_fail(e2, "launch_count", __LINE__);
   }
   *out = h;
   return SIM_OK;
@@ -323,9 +331,9 @@ int sim_stats(sim_handle* h, sim_stats_t* out, void* stream) {
   if (!h || !out) return SIM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   unsigned long long v[kTileStatFields];
-  if (launch_reduce_counts(h->stats, h->stats_entries, h->totals, s) != hipSuccess) return SIM_EHIP;
-  if (hipMemcpyAsync(v, h->totals, sizeof(v), hipMemcpyDeviceToHost, s) != hipSuccess) return SIM_EHIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return SIM_EHIP;
+  PEDSIM_HIP(launch_reduce_counts(h->stats, h->stats_entries, h->totals, s));
+  PEDSIM_HIP(hipMemcpyAsync(v, h->totals, sizeof(v), hipMemcpyDeviceToHost, s));
+  PEDSIM_HIP(hipStreamSynchronize(s));
   out->step = h->t;
   out->agents_a = v[0];
   out->agents_b = v[1];
@@ -339,13 +347,10 @@ int sim_read_state(sim_handle* h, uint8_t* code, uint32_t* id, float* tau, void*
   if (!h) return SIM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   const size_t cells = (size_t)h->p.W * (size_t)h->p.H;
-  if (code && hipMemcpyAsync(code, h->user.code, cells, hipMemcpyDefault, s) != hipSuccess) return SIM_EHIP;
-  if (id && hipMemcpyAsync(id, h->user.id, cells * sizeof(uint32_t), hipMemcpyDefault, s) != hipSuccess)
-    return SIM_EHIP;
-  if (tau && h->user.tau &&
-      hipMemcpyAsync(tau, h->user.tau, 2 * cells * sizeof(float), hipMemcpyDefault, s) != hipSuccess)
-    return SIM_EHIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return SIM_EHIP;
+  if (code) PEDSIM_HIP(hipMemcpyAsync(code, h->user.code, cells, hipMemcpyDefault, s));
+  if (id) PEDSIM_HIP(hipMemcpyAsync(id, h->user.id, cells * sizeof(uint32_t), hipMemcpyDefault, s));
+  if (tau && h->user.tau) PEDSIM_HIP(hipMemcpyAsync(tau, h->user.tau, 2 * cells * sizeof(float), hipMemcpyDefault, s));
+  PEDSIM_HIP(hipStreamSynchronize(s));
   return SIM_OK;
 }
 
@@ -355,16 +360,19 @@ int sim_step_timed(sim_handle* h, int32_t mode, int32_t nsteps, void* stream, do
   if (mode != kModeLem && mode != kModeAco) return SIM_EINVAL;
   if (mode == kModeAco && !h->user.tau) return SIM_ENOTAU;
   hipEvent_t ev[2];
-  if (hipEventCreate(&ev[0]) != hipSuccess) return SIM_EHIP;
-  if (hipEventCreate(&ev[1]) != hipSuccess) {
+  PEDSIM_HIP(hipEventCreate(&ev[0]));
+  const hipError_t e1 = hipEventCreate(&ev[1]);
+  if (e1 != hipSuccess) {
     (void)hipEventDestroy(ev[0]);
-    return SIM_EHIP;
+    return hip_fail(e1, "hipEventCreate", __LINE__);
   }
   const int rc = run_steps(h, mode, nsteps, (hipStream_t)stream, ev, kernel_ms, launches);
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
   return rc == SIM_OK ? 2 : rc;
 }
+
+const char* sim_last_error(void) { return g_last_error; }
 
 const char* sim_kernel_name(int32_t kind) {
   switch (kind) {

@@ -70,6 +70,15 @@ struct ScratchLayout {
   int stats_cap;
 };
 
+// Record a failed HIP call for sim_last_error() (per thread) and return
+// SIM_EHIP.
+int hip_fail(hipError_t e, const char* what, int line);
+#define PEDSIM_HIP(expr)                                                         \
+  do {                                                                           \
+    const hipError_t pedsim_e_ = (expr);                                         \
+    if (pedsim_e_ != hipSuccess) return ::pedsim::hip_fail(pedsim_e_, #expr, __LINE__); \
+  } while (0)
+
 ScratchLayout layout_of(const sim_params* p);
 int check_params(const sim_params* p);
 Scenario base_scenario(const sim_params* p);

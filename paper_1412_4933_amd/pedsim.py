@@ -24,7 +24,10 @@ SIM_MODE_LEM, SIM_MODE_ACO = 0, 1
 class SimError(RuntimeError):
     def __init__(self, code: int, what: str):
         self.code = code
-        super().__init__(f"{what}: {sim_strerror(code)} ({code})")
+        detail = ""
+        if code == SIM_EHIP:
+            detail = " [" + lib().sim_last_error().decode(errors="replace") + "]"
+        super().__init__(f"{what}: {sim_strerror(code)} ({code}){detail}")
 
 
 class SimParams(ctypes.Structure):
@@ -58,6 +61,8 @@ def lib() -> ctypes.CDLL:
         P = ctypes.POINTER
         L.sim_strerror.argtypes = [ctypes.c_int]
         L.sim_strerror.restype = ctypes.c_char_p
+        L.sim_last_error.argtypes = []
+        L.sim_last_error.restype = ctypes.c_char_p
         L.sim_scratch_bytes.argtypes = [P(SimParams), P(sz)]
         L.sim_create.argtypes = [P(SimParams), vp, vp, vp, vp, sz, vp, P(vp)]
         L.sim_step_lem.argtypes = [vp, i32, vp]

@@ -1,6 +1,8 @@
 """Host-side checks of the C ABI: the library loads, exports every symbol the
 header declares, and rejects bad arguments before touching the GPU."""
 import ctypes
+
+import numpy as np
 import os
 import re
 
@@ -90,3 +92,25 @@ def test_scenario_bands_follow_the_band_rule():
     assert np.all(s.code[:, 99:1024 - 99] != scenarios.GROUP_A)
     assert np.count_nonzero(s.code == scenarios.GROUP_A) == 50000
     assert sorted(s.ids[s.ids != 0].tolist()) == list(range(1, 100001))
+
+
+def test_serving_requests_are_poisson_and_sized():
+    from paper_1412_4933_amd import serve
+    specs = scenarios.served_requests(64)
+    reqs = serve.poisson_requests(specs, rate=100.0, seed=1)
+    t = [r.arrival for r in reqs]
+    assert all(b > a for a, b in zip(t, t[1:]))
+    gaps = np.diff([0.0] + t)
+    assert 0.005 < gaps.mean() < 0.02  # rate 100/s
+    for r, (W, H, N, band, mode, steps, seed) in zip(reqs, specs):
+        assert 200 <= r.steps <= 2000 and r.agents == N
+        assert r.nbytes >= W * H * (5 + (8 if mode == 1 else 0))
+
+
+def test_batch_shapes_follow_the_recipe():
+    shapes = scenarios.batch_shapes(256)
+    assert len(shapes) == 256
+    for i, (W, H, N, band, mode) in enumerate(shapes):
+        assert 64 <= W <= 2048 and W % 2 == 0 and H == W // 2
+        assert 500 <= N <= 100000 and N % 2 == 0 and N <= 2 * (W // 4) * (H - 2)
+        assert mode == (i % 2)

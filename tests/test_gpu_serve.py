@@ -1,0 +1,69 @@
+"""Served form: continuous batching with HBM-budget admission. Every request's
+result equals its result alone, requests overlap on the device, and the
+budget holds requests back."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1412_4933_amd import scenarios as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1412_4933_amd import pedsim, serve
+    pedsim.lib()
+    return pedsim, serve
+
+
+def small_specs(n, seed=11):
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(n):
+        W = int(rng.integers(30, 200))
+        H = int(rng.integers(10, 80))
+        N = int(rng.integers(10, min(2 * (W // 4) * (H - 2), 2500)))
+        mode = S.MODE_LEM if i % 2 else S.MODE_ACO
+        specs.append((W, H, N, max(1, W // 10), mode, int(rng.integers(20, 140)), 900 + i))
+    return specs
+
+
+def test_served_results_equal_alone_runs_and_overlap(mods):
+    pedsim, serve = mods
+    specs = small_specs(14)
+    reqs = serve.poisson_requests(specs, rate=400.0, seed=3)
+    budget = sorted(r.nbytes for r in reqs)[-1] * 3  # about three scenarios fit at once
+    print("[gpu-case] served", len(reqs), "budget", budget, flush=True)
+    srv = serve.Server(capacity=4, budget_bytes=budget, quantum=16, keep_state=True)
+    results = srv.run(reqs)
+    srv.close()
+    assert sorted(r.rid for r in results) == list(range(len(reqs)))
+    by_id = {r.rid: r for r in results}
+    overlapped = 0
+    for req in reqs:
+        res = by_id[req.rid]
+        scn = req.build()
+        st = oracle.State.from_scenario(scn)
+        st.run(scn.mode, req.steps)
+        code, ids, tau = res.state
+        assert np.array_equal(code, st.code) and np.array_equal(ids, st.ids), req.rid
+        if scn.mode == S.MODE_ACO:
+            assert np.array_equal(tau.view(np.uint32), st.tau.view(np.uint32)), req.rid
+        assert res.stats["step"] == req.steps
+        others = [o for o in results if o.rid != res.rid and o.admitted < res.finished and o.finished > res.admitted]
+        overlapped += bool(others)
+    assert overlapped >= len(reqs) // 2  # requests shared the device
+    assert any(r.admitted > r.arrival + 1e-4 for r in results)  # admission waited for room
+
+
+def test_served_request_larger_than_budget_is_refused(mods):
+    pedsim, serve = mods
+    reqs = serve.poisson_requests(small_specs(2, seed=5), rate=1000.0)
+    srv = serve.Server(capacity=2, budget_bytes=min(r.nbytes for r in reqs) - 1, quantum=8)
+    with pytest.raises(ValueError):
+        srv.run(reqs)
+    srv.close()
