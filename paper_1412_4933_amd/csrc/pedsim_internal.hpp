@@ -7,6 +7,7 @@
 
 #include "rules.hpp"
 #include "tile_engine.hpp"
+#include "tile_wave.hpp"
 
 namespace pedsim {
 
@@ -15,7 +16,7 @@ constexpr int kModeAco = 1;
 
 // Tiling of one scenario for the tile engine: regions of 64*nw columns x
 // rows, advanced `steps` steps per launch (halo 3*steps), `threads` per
-// workgroup.
+// workgroup. threads == 64 selects the one-wave engine (nw == 1, rows <= 64).
 struct Tiling {
   int nw;       // 1 or 2 words per row
   int rows;     // region rows, <= threads
@@ -27,6 +28,7 @@ struct Tiling {
 constexpr int kMinInteriorX = 16;
 constexpr int kMinInteriorY = 8;
 
+inline bool one_wave(const Tiling& tl) { return tl.threads == 64; }
 size_t tile_lds_bytes(const Tiling& tl, bool aco);
 bool tiling_valid(const Tiling& tl, bool aco, int max_lds);
 

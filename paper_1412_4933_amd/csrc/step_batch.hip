@@ -50,6 +50,45 @@ __global__ __launch_bounds__(1024) void batch_kernel(BatchPlan P, int j) {
   }
 }
 
+// The same with the one-wave engine (64-lane workgroups).
+__global__ __launch_bounds__(64) void batch_wave_kernel(BatchPlan P, int j) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  int& s_item = *(int*)(smem + WaveLayout{P.rows, P.k}.bytes());
+  const int count = P.counts[j];
+  const int total = P.totals[j];
+  const BatchEntry* E = P.entries + (size_t)j * P.capacity;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(&P.counters[j], 1u);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (item >= total) break;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (E[mid].first <= item) lo = mid; else hi = mid - 1;
+    }
+    const BatchSlot& B = P.slots[E[lo].slot];
+    Scenario S = B.S;
+    const int par = j & 1;
+    S.code_in = B.code[par];
+    S.id_in = B.id[par];
+    S.tau_in = B.tau[par];
+    S.code_out = B.code[par ^ 1];
+    S.id_out = B.id[par ^ 1];
+    S.tau_out = B.tau[par ^ 1];
+    const int done = j * P.k;
+    const int steps = B.steps - done < P.k ? B.steps - done : P.k;
+    const bool last = done + steps == B.steps;
+    const int tile = item - E[lo].first;
+    const int tx = tile % S.tiles_x, ty = tile / S.tiles_x;
+    if (B.mode == kModeAco)
+      advance_tile_wave<kModeAco>(S, smem, P.rows, P.k, tx, ty, tile, B.t0 + (uint64_t)done, steps, last);
+    else
+      advance_tile_wave<kModeLem>(S, smem, P.rows, P.k, tx, ty, tile, B.t0 + (uint64_t)done, steps, last);
+  }
+}
+
 __global__ void batch_reset_kernel(unsigned* counters, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) counters[i] = 0u;
 }
@@ -97,6 +136,11 @@ static hipError_t launch_batch_nw(const BatchPlan& P, const Tiling& tl, int j, i
 }
 
 hipError_t launch_batch(const BatchPlan& P, const Tiling& tl, int j, int grid, hipStream_t s) {
+  if (one_wave(tl)) {
+    const size_t lds = WaveLayout{tl.rows, tl.steps}.bytes() + kBatchItemBytes;
+    batch_wave_kernel<<<grid, 64, lds, s>>>(P, j);
+    return hipGetLastError();
+  }
   return tl.nw == 1 ? launch_batch_nw<1>(P, tl, j, grid, s) : launch_batch_nw<2>(P, tl, j, grid, s);
 }
 

@@ -251,8 +251,10 @@ def test_aco_without_pheromone_refused(pedsim):
     sim.close()
 
 
-TILINGS = [(1, 32, 1, 256), (1, 48, 2, 512), (1, 64, 3, 1024), (2, 40, 1, 64 * 1), (2, 64, 2, 1024),
-           (2, 64, 4, 1024), (1, 96, 2, 128)]
+TILINGS = [(1, 32, 1, 256), (1, 48, 2, 512), (1, 64, 3, 1024), (2, 64, 2, 1024), (2, 64, 4, 1024),
+           (1, 96, 2, 128),
+           # one-wave engine (64-lane workgroups)
+           (1, 32, 1, 64), (1, 48, 2, 64), (1, 64, 3, 64), (1, 64, 1, 64)]
 
 
 @pytest.mark.parametrize("mode", [S.MODE_LEM, S.MODE_ACO])
@@ -277,4 +279,4 @@ def test_results_do_not_depend_on_tiling(pedsim, mode):
         assert_same(sim, st, f"tiling {tl}")
         sim.close()
         ran += 1
-    assert ran >= 4
+    assert ran >= 8
