@@ -56,6 +56,11 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        # torch's HIP runtime must be the one in the process before the library
+        # is loaded: torch asks the dynamic linker for a runtime by a name that
+        # does not match the versioned name the library links against, so the
+        # library loaded first would leave two HIP runtimes side by side.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
         P = ctypes.POINTER

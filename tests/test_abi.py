@@ -114,3 +114,10 @@ def test_batch_shapes_follow_the_recipe():
         assert 64 <= W <= 2048 and W % 2 == 0 and H == W // 2
         assert 500 <= N <= 100000 and N % 2 == 0 and N <= 2 * (W // 4) * (H - 2)
         assert mode == (i % 2)
+
+
+def test_library_loads_after_torch_runtime():
+    """The library shares torch's HIP runtime: loading it brings torch in first."""
+    import sys
+    pedsim.lib()
+    assert "torch" in sys.modules
