@@ -204,6 +204,8 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=2.0, help="HBM budget for resident scenarios")
     ap.add_argument("--quantum", type=int, default=100, help="steps per serving quantum")
     ap.add_argument("--no-serve", action="store_true", help="skip the served run of the default line")
+    ap.add_argument("--tiling", default=None,
+                    help="nw,rows,steps_per_launch,threads for the step kernel (default: the library's)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
@@ -235,12 +237,20 @@ def main():
 
     # warmup on a throwaway copy, then time K steps from the initial state
     log(f"workload {args.workload}: {scn.W}x{scn.H}, {agents} agents, mode {mode}, K={K}")
+    tiling_arg = tuple(int(v) for v in args.tiling.split(",")) if args.tiling else None
+
+    def make_sim():
+        sim = pedsim.Sim(scn, stream=stream)
+        if tiling_arg is not None:
+            sim.set_tiling(mode, *tiling_arg)
+        return sim
+
     if args.warmup > 0:
-        w = pedsim.Sim(scn, stream=stream)
+        w = make_sim()
         w.step(args.warmup, mode)
         w.stats()
         w.close()
-    sim = pedsim.Sim(scn, stream=stream)
+    sim = make_sim()
     torch.cuda.synchronize(dev)
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
@@ -258,7 +268,7 @@ def main():
     log(f"timed {K} steps: {ms:.3f} ms (wall {wall * 1e3:.3f} ms), stats {stats}")
 
     # per-launch durations of the step kernel with HIP events on the launch stream
-    prof = pedsim.Sim(scn, stream=stream)
+    prof = make_sim()
     tiling = pedsim.sim_get_tiling(prof.h, mode)
     per_kernel = pedsim.sim_step_timed(prof.h, mode, K, stream)
     prof.close()
@@ -267,8 +277,8 @@ def main():
     # The timed region above ran exactly these launches back to back on
     # `stream`: the step kernel's average duration is the region's event time
     # (minus the copy-back launches, if any) over its launch count.
-    dom = "tile_kernel"
-    dom_n = per_kernel[dom][1]
+    dom_n = per_kernel["tile_kernel"][1]
+    dom = "tile_rows_kernel" if tiling[0] == 0 else "tile_kernel"  # kernel symbol in traces
     copy_ms = per_kernel["copy_back"][0]
     dom_avg_ms = (ms - copy_ms) / dom_n
     alg_step = algorithmic_bytes_per_step(mode, cells, agents)

@@ -127,10 +127,13 @@ int sim_read_state(sim_handle* h, uint8_t* code, uint32_t* id, float* tau, void*
 /*
  * Tiling of the step kernel for `mode` (results never depend on it): each
  * workgroup of `threads` lanes (multiple of 64, <= 1024) stages a region of
- * 64*nw columns (nw = 1 or 2) x `rows` rows (rows <= threads) in LDS and
- * advances it `steps_per_launch` steps per launch; the tile interior is the
- * region minus 3*steps_per_launch cells on every side and must be at least
- * 16 x 8. SIM_EINVAL if the shape is not allowed or does not fit the LDS.
+ * `rows` rows in LDS and advances it `steps_per_launch` steps per launch; the
+ * tile interior is the region minus 3*steps_per_launch cells on every side
+ * and must be at least 16 x 8.
+ *   nw = 1 or 2: multi-wave engine, regions of 64*nw columns (rows <= 1023);
+ *   nw = 0:      row-lane engine, regions of 64 columns, rows <= 64,
+ *                steps_per_launch <= 8.
+ * SIM_EINVAL if the shape is not allowed or does not fit the LDS.
  * sim_get_tiling writes {nw, rows, steps_per_launch, threads} into out[4].
  */
 int sim_set_tiling(sim_handle* h, int32_t mode, int32_t nw, int32_t rows, int32_t steps_per_launch,

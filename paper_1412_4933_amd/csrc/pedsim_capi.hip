@@ -80,7 +80,7 @@ Scenario base_scenario(const sim_params* p) {
 
 void set_geometry(Scenario& S, const Tiling& tl) {
   S.halo = 3 * tl.steps;
-  S.IX = 64 * tl.nw - 2 * S.halo;
+  S.IX = region_cols(tl) - 2 * S.halo;
   S.IY = tl.rows - 2 * S.halo;
   S.tiles_x = (S.W + S.IX - 1) / S.IX;
   S.tiles_y = (S.H + S.IY - 1) / S.IY;
@@ -116,12 +116,13 @@ using namespace pedsim;
 
 namespace {
 
-// Default tiling by grid size (measured on MI355X): small grids want many
-// small tiles so every CU has one; large grids want tall regions and three
-// steps per launch. The first shape that fits the device's LDS is used.
+// Default tiling by grid size (measured on MI355X): the row-lane engine on
+// 48-row regions, three steps per launch below 2M cells and two above (more
+// steps per launch widen the halo faster than they save launches there).
+// The first shape that fits the device's LDS is used.
 Tiling default_tiling(bool aco, size_t cells) {
-  static const Tiling small_opts[] = {{1, 32, 2, 512}, {1, 24, 2, 256}, {1, 32, 1, 256}};
-  static const Tiling large_opts[] = {{1, 128, 3, 1024}, {1, 64, 3, 512}, {1, 32, 1, 256}};
+  static const Tiling small_opts[] = {{0, 48, 3, 512}, {0, 32, 2, 256}, {1, 32, 1, 256}};
+  static const Tiling large_opts[] = {{0, 48, 2, 512}, {0, 32, 2, 256}, {1, 32, 1, 256}};
   const Tiling* opts = cells < ((size_t)2 << 20) ? small_opts : large_opts;
   for (int i = 0; i < 3; ++i)
     if (tiling_valid(opts[i], aco, max_dynamic_lds())) return opts[i];

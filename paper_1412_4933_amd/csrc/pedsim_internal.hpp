@@ -7,19 +7,20 @@
 
 #include "rules.hpp"
 #include "tile_engine.hpp"
-#include "tile_wave.hpp"
+#include "tile_rows.hpp"
 
 namespace pedsim {
 
 constexpr int kModeLem = 0;
 constexpr int kModeAco = 1;
 
-// Tiling of one scenario for the tile engine: regions of 64*nw columns x
-// rows, advanced `steps` steps per launch (halo 3*steps), `threads` per
-// workgroup. threads == 64 selects the one-wave engine (nw == 1, rows <= 64).
+// Tiling of one scenario: regions of `rows` rows advanced `steps` steps per
+// launch (halo 3*steps), `threads` per workgroup. nw = 1 or 2 selects the
+// multi-wave engine on regions of 64*nw columns; nw = 0 selects the row-lane
+// engine on regions of 64 columns and at most 64 rows.
 struct Tiling {
-  int nw;       // 1 or 2 words per row
-  int rows;     // region rows, <= threads
+  int nw;       // 0 (row-lane engine), 1 or 2 (multi-wave engine, words per row)
+  int rows;     // region rows
   int steps;    // steps per launch (>= 1)
   int threads;  // workgroup size, multiple of 64, <= 1024
 };
@@ -28,7 +29,8 @@ struct Tiling {
 constexpr int kMinInteriorX = 16;
 constexpr int kMinInteriorY = 8;
 
-inline bool one_wave(const Tiling& tl) { return tl.threads == 64; }
+inline bool rows_engine(const Tiling& tl) { return tl.nw == 0; }
+inline int region_cols(const Tiling& tl) { return tl.nw == 0 ? 64 : 64 * tl.nw; }
 size_t tile_lds_bytes(const Tiling& tl, bool aco);
 bool tiling_valid(const Tiling& tl, bool aco, int max_lds);
 

@@ -50,10 +50,10 @@ __global__ __launch_bounds__(1024) void batch_kernel(BatchPlan P, int j) {
   }
 }
 
-// The same with the one-wave engine (64-lane workgroups).
-__global__ __launch_bounds__(64) void batch_wave_kernel(BatchPlan P, int j) {
+// The same with the row-lane engine (regions of 64 columns).
+__global__ __launch_bounds__(1024) void batch_rows_kernel(BatchPlan P, int j) {
   extern __shared__ __align__(16) uint8_t smem[];
-  int& s_item = *(int*)(smem + WaveLayout{P.rows, P.k}.bytes());
+  int& s_item = *(int*)(smem + RowsLayout{P.rows, P.k, true}.bytes());
   const int count = P.counts[j];
   const int total = P.totals[j];
   const BatchEntry* E = P.entries + (size_t)j * P.capacity;
@@ -83,9 +83,9 @@ __global__ __launch_bounds__(64) void batch_wave_kernel(BatchPlan P, int j) {
     const int tile = item - E[lo].first;
     const int tx = tile % S.tiles_x, ty = tile / S.tiles_x;
     if (B.mode == kModeAco)
-      advance_tile_wave<kModeAco>(S, smem, P.rows, P.k, tx, ty, tile, B.t0 + (uint64_t)done, steps, last);
+      advance_tile_rows<kModeAco>(S, smem, P.rows, P.k, tx, ty, tile, B.t0 + (uint64_t)done, steps, last);
     else
-      advance_tile_wave<kModeLem>(S, smem, P.rows, P.k, tx, ty, tile, B.t0 + (uint64_t)done, steps, last);
+      advance_tile_rows<kModeLem>(S, smem, P.rows, P.k, tx, ty, tile, B.t0 + (uint64_t)done, steps, last);
   }
 }
 
@@ -124,6 +124,8 @@ void prepare_batch_kernels() {
                             max_dynamic_lds());
   (void)hipFuncSetAttribute((const void*)batch_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             max_dynamic_lds());
+  (void)hipFuncSetAttribute((const void*)batch_rows_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            max_dynamic_lds());
   (void)hipGetLastError();  // an unsupported attribute value must not linger as the last error
   done = true;
 }
@@ -136,9 +138,9 @@ static hipError_t launch_batch_nw(const BatchPlan& P, const Tiling& tl, int j, i
 }
 
 hipError_t launch_batch(const BatchPlan& P, const Tiling& tl, int j, int grid, hipStream_t s) {
-  if (one_wave(tl)) {
-    const size_t lds = WaveLayout{tl.rows, tl.steps}.bytes() + kBatchItemBytes;
-    batch_wave_kernel<<<grid, 64, lds, s>>>(P, j);
+  if (rows_engine(tl)) {
+    const size_t lds = RowsLayout{tl.rows, tl.steps, true}.bytes() + kBatchItemBytes;
+    batch_rows_kernel<<<grid, tl.threads, lds, s>>>(P, j);
     return hipGetLastError();
   }
   return tl.nw == 1 ? launch_batch_nw<1>(P, tl, j, grid, s) : launch_batch_nw<2>(P, tl, j, grid, s);

@@ -22,26 +22,26 @@ __global__ __launch_bounds__(1024) void tile_kernel(Scenario S, int R, uint64_t 
 }
 
 template <int MODE>
-__global__ __launch_bounds__(64) void tile_wave_kernel(Scenario S, int R, int k_max, uint64_t t0, int steps,
-                                                       int last) {
+__global__ __launch_bounds__(1024) void tile_rows_kernel(Scenario S, int R, int k_max, uint64_t t0, int steps,
+                                                         int last) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int ntiles = S.tiles_x * S.tiles_y;
   const int tile = tile_of_block(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
-  advance_tile_wave<MODE>(S, smem, R, k_max, tile % S.tiles_x, tile / S.tiles_x, tile, t0, steps, last != 0);
+  advance_tile_rows<MODE>(S, smem, R, k_max, tile % S.tiles_x, tile / S.tiles_x, tile, t0, steps, last != 0);
 }
 
 size_t tile_lds_bytes(const Tiling& tl, bool aco) {
-  if (one_wave(tl)) return WaveLayout{tl.rows, tl.steps}.bytes();
+  if (rows_engine(tl)) return RowsLayout{tl.rows, tl.steps, aco}.bytes();
   return tl.nw == 1 ? Layout<1>{tl.rows, aco}.bytes() : Layout<2>{tl.rows, aco}.bytes();
 }
 
 bool tiling_valid(const Tiling& tl, bool aco, int max_lds) {
-  if (tl.nw != 1 && tl.nw != 2) return false;
-  if (one_wave(tl) && (tl.nw != 1 || tl.rows > kWaveMaxRows || tl.steps > kWaveMaxSteps)) return false;
+  if (tl.nw < 0 || tl.nw > 2) return false;
+  if (rows_engine(tl) && (tl.rows > kRowsMaxRows || tl.steps > kRowsMaxSteps)) return false;
   if (tl.steps < 1 || tl.threads < 64 || tl.threads > 1024 || tl.threads % 64) return false;
   if (tl.rows < 1 || tl.rows > 1023) return false;
-  if (64 * tl.nw - 6 * tl.steps < kMinInteriorX || tl.rows - 6 * tl.steps < kMinInteriorY) return false;
+  if (region_cols(tl) - 6 * tl.steps < kMinInteriorX || tl.rows - 6 * tl.steps < kMinInteriorY) return false;
   return tile_lds_bytes(tl, aco) <= (size_t)max_lds;
 }
 
@@ -74,19 +74,26 @@ static hipError_t launch_one(const Scenario& S, const Tiling& tl, uint64_t t0, i
 }
 
 template <int MODE>
-static hipError_t launch_wave(const Scenario& S, const Tiling& tl, uint64_t t0, int steps, int last, hipStream_t s) {
-  const size_t lds = WaveLayout{tl.rows, tl.steps}.bytes();
+static hipError_t launch_rows(const Scenario& S, const Tiling& tl, uint64_t t0, int steps, int last, hipStream_t s) {
+  const size_t lds = RowsLayout{tl.rows, tl.steps, MODE == kModeAco}.bytes();
+  static bool attr_done = false;
+  if (!attr_done) {
+    (void)hipFuncSetAttribute((const void*)tile_rows_kernel<MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              max_dynamic_lds());
+    (void)hipGetLastError();  // an unsupported attribute value must not linger as the last error
+    attr_done = true;
+  }
   const int ntiles = S.tiles_x * S.tiles_y;
   const int blocks = ((ntiles + 7) / 8) * 8;
-  tile_wave_kernel<MODE><<<blocks, 64, lds, s>>>(S, tl.rows, tl.steps, t0, steps, last);
+  tile_rows_kernel<MODE><<<blocks, tl.threads, lds, s>>>(S, tl.rows, tl.steps, t0, steps, last);
   return hipGetLastError();
 }
 
 hipError_t launch_tiles(const Scenario& S, const Tiling& tl, int mode, uint64_t t0, int steps, int last,
                         hipStream_t s) {
-  if (one_wave(tl))
-    return mode == kModeLem ? launch_wave<kModeLem>(S, tl, t0, steps, last, s)
-                            : launch_wave<kModeAco>(S, tl, t0, steps, last, s);
+  if (rows_engine(tl))
+    return mode == kModeLem ? launch_rows<kModeLem>(S, tl, t0, steps, last, s)
+                            : launch_rows<kModeAco>(S, tl, t0, steps, last, s);
   if (tl.nw == 1)
     return mode == kModeLem ? launch_one<1, kModeLem>(S, tl, t0, steps, last, s)
                             : launch_one<1, kModeAco>(S, tl, t0, steps, last, s);

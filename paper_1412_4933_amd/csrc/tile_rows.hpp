@@ -1,0 +1,411 @@
+// Row-lane tile engine: one workgroup advances one tile of a scenario by k
+// steps of the bi-directional pedestrian update (Sec. III, Sec. IV.b-d).
+//
+// The region is 64 columns x R rows (R <= 64) around the tile: the interior
+// plus a halo of 3k cells on every side, as in the multi-wave engine (after
+// k steps the cells at least 3k from the region border are exact). Outside
+// the region counts as wall.
+//
+// Wave 0 is the mask wave: lane r owns row r, whose A, B and wall masks (one
+// bit per cell) stay in its registers for the whole launch; rows r-1 and r+1
+// are read with full-wave DPP shifts. Every decision that follows from
+// occupancy alone is mask arithmetic in that wave: forward requests, side
+// requests of agents with exactly one empty side candidate (LEM and ACO both
+// take the only candidate), the cells that can possibly be contested, and the
+// commit. Only agents that draw a choice (two or more empty side candidates)
+// or that may meet a contest need their Philox words; they are queued and
+// all waves draw them together, so a step has one Philox pass, and its word
+// 0 is kept as the agent's ticket for the resolution.
+//
+// Per step (B = workgroup barrier):
+//   1. masks     (wave 0) forward requests, single-candidate side requests,
+//                possibly contested cells; queue the agents that draw   B
+//   2. draw      (all) Philox words, tickets, LEM (eq. 1) / ACO (eq. 2)
+//                choices or-ed into side-request masks                  B
+//   3. gather    (wave 0) requester masks per target, in eight
+//                directions; queue every requested cell                 B
+//   4. resolve   (all) contested cells keep the lowest (ticket, agent
+//                number) (Sec. IV.d); every winner's id moves to its
+//                target (targets were empty and sources occupied at the
+//                start of the step, so the moves never overlap)         B
+//   5. commit    (wave 0) new occupancy, recorded in an LDS history.
+// Ids live in LDS; the pheromone planes are staged in LDS and never rewritten
+// during the launch: a cell's value after s steps is fl(keep * v) (+ dtau when
+// the group occupies it) applied s times, using the recorded occupancy,
+// exactly the per-step update of eq. 3 then eq. 4; it is evaluated where
+// needed (ACO candidates in step 2, every interior cell at write-back).
+#pragma once
+
+#include "rules.hpp"
+#include "tile_engine.hpp"
+
+namespace pedsim {
+
+constexpr int kRowsMaxRows = 64;
+constexpr int kRowsMaxSteps = 8;
+
+// LDS layout of a row-lane region of R rows x 64 columns, k steps per launch.
+struct RowsLayout {
+  int R, k;
+  bool aco;
+  __host__ __device__ size_t hist() const { return 0; }                                  // [k+1][2][R] u64
+  __host__ __device__ size_t wall() const { return hist() + (size_t)(k + 1) * 2 * R * 8; }  // [R] u64
+  __host__ __device__ size_t side() const { return wall() + (size_t)R * 8; }             // [6][R] u64
+  __host__ __device__ size_t reqm() const { return side() + (size_t)6 * R * 8; }         // [8][R] u64
+  __host__ __device__ size_t cwin() const { return reqm() + (size_t)8 * R * 8; }         // [8][R] u64
+  __host__ __device__ size_t moved() const { return cwin() + (size_t)8 * R * 8; }        // [R] u64
+  __host__ __device__ size_t ctl() const { return moved() + (size_t)R * 8; }             // 16 u32
+  __host__ __device__ size_t ids() const { return ctl() + 64; }                         // [R][64] u32
+  __host__ __device__ size_t tick() const { return ids() + (size_t)R * 256; }           // [R][64] u32
+  __host__ __device__ size_t queue() const { return tick() + (size_t)R * 256; }         // [R*64] u32
+  __host__ __device__ size_t tau() const { return queue() + (size_t)R * 256; }          // [2][R][64] f32
+  __host__ __device__ size_t bytes() const { return tau() + (aco ? (size_t)R * 512 : 0); }
+};
+
+// Row r-1's value in lane r (0 in lane 0) / row r+1's value in lane r (0 in lane 63).
+__device__ __forceinline__ uint64_t from_up(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)v, 0x138, 0xF, 0xF, false);  // wave_shr:1
+  const uint32_t hi = __builtin_amdgcn_update_dpp(0u, (uint32_t)(v >> 32), 0x138, 0xF, 0xF, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t from_down(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)v, 0x130, 0xF, 0xF, false);  // wave_shl:1
+  const uint32_t hi = __builtin_amdgcn_update_dpp(0u, (uint32_t)(v >> 32), 0x130, 0xF, 0xF, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Number of lanes below this one whose bit is set in `bal`.
+__device__ __forceinline__ int lanes_below(uint64_t bal) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+}
+
+// Wave 0: append (row = lane, column) of every set bit of `bits` to `queue`;
+// returns the number appended (wave-uniform). Lanes take turns bit by bit,
+// so the loop runs as many times as the fullest row has bits.
+__device__ __forceinline__ int enqueue_row_bits(uint32_t* queue, uint64_t bits, int lane) {
+  int base = 0;
+  for (;;) {
+    const bool has = bits != 0ull;
+    const uint64_t bal = __ballot(has);
+    if (bal == 0ull) break;
+    if (has) {
+      const int c = __ffsll((unsigned long long)bits) - 1;
+      bits &= bits - 1ull;
+      queue[base + lanes_below(bal)] = (uint32_t)lane | ((uint32_t)c << 6);
+    }
+    base += __popcll(bal);
+  }
+  return base;
+}
+
+template <int MODE>
+__device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k_max, int tx, int ty, int tile_index,
+                                  uint64_t t0, int steps, bool last) {
+  const RowsLayout L{R, k_max, MODE == 1};
+  uint64_t* hist = (uint64_t*)(smem + L.hist());
+  uint64_t* wall_m = (uint64_t*)(smem + L.wall());
+  uint64_t* side = (uint64_t*)(smem + L.side());
+  uint64_t* reqm = (uint64_t*)(smem + L.reqm());
+  uint64_t* cwin = (uint64_t*)(smem + L.cwin());
+  uint64_t* moved_m = (uint64_t*)(smem + L.moved());
+  uint32_t* ctl = (uint32_t*)(smem + L.ctl());
+  uint32_t* ids = (uint32_t*)(smem + L.ids());
+  uint32_t* tick = (uint32_t*)(smem + L.tick());
+  uint32_t* queue = (uint32_t*)(smem + L.queue());
+  float* tau_a = (float*)(smem + L.tau());
+  float* tau_b = tau_a + (size_t)R * 64;
+  // occupancy of group g (0 = A, 1 = B) at step s of the launch, row r
+  auto H = [&](int s, int g, int r) -> uint64_t& { return hist[((size_t)s * 2 + g) * R + r]; };
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int nthreads = blockDim.x;
+  const int nwaves = nthreads >> 6;
+  const bool mask_wave = wave == 0;
+  const bool row_lane = lane < R;
+  const int h = S.halo;
+  const int x0 = tx * S.IX - h;  // region origin in grid coordinates
+  const int y0 = ty * S.IY - h;
+  const size_t plane = (size_t)S.W * (size_t)S.H;
+  const uint64_t lane_bit = 1ull << lane;
+
+  // ---- stage: all loads of a wave's rows in flight together ---------------
+  constexpr int kStageRows = 8;
+  for (int r0 = wave * kStageRows; r0 < R; r0 += nwaves * kStageRows) {
+    int g[kStageRows];
+    uint32_t idv[kStageRows];
+    float ta[kStageRows], tb[kStageRows];
+#pragma unroll
+    for (int j = 0; j < kStageRows; ++j) {
+      const int gx = x0 + lane, gy = y0 + r0 + j;
+      const bool in = r0 + j < R && gx >= 0 && gx < S.W && gy >= 0 && gy < S.H;
+      const size_t gi = in ? (size_t)gy * S.W + gx : 0;
+      g[j] = in ? S.code_in[gi] : kWall;
+      idv[j] = in ? S.id_in[gi] : 0u;
+      if (MODE == 1) {
+        ta[j] = in ? S.tau_in[gi] : 0.0f;
+        tb[j] = in ? S.tau_in[plane + gi] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kStageRows; ++j) {
+      const int r = r0 + j;
+      if (r >= R) break;
+      const uint64_t ba = __ballot(g[j] == kGroupA), bb = __ballot(g[j] == kGroupB);
+      const uint64_t bw = __ballot(g[j] == kWall);
+      if (lane == 0) {
+        H(0, 0, r) = ba;
+        H(0, 1, r) = bb;
+        wall_m[r] = bw;
+      }
+      ids[r * 64 + lane] = idv[j];
+      if (MODE == 1) {
+        tau_a[r * 64 + lane] = ta[j];
+        tau_b[r * 64 + lane] = tb[j];
+      }
+    }
+  }
+  if (tid < 16) ctl[tid] = 0u;
+  __syncthreads();
+
+  // the mask wave's registers: row `lane` of the region (rows >= R: all wall)
+  uint64_t A = 0ull, B = 0ull, Wl = ~0ull;
+  if (mask_wave && row_lane) {
+    A = H(0, 0, lane);
+    B = H(0, 1, lane);
+    Wl = wall_m[lane];
+  }
+  uint64_t moved_in = 0ull;
+  uint64_t fA = 0ull, fB = 0ull;
+  uint64_t rq[6] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+  uint64_t Wt[8];
+
+  for (int s = 0; s < steps; ++s) {
+    const uint64_t t = t0 + (uint64_t)s;
+
+    // ---- 1. masks: requests that need no random word; who must draw -------
+    if (mask_wave) {
+      const uint64_t E = ~(A | B | Wl);
+      const uint64_t Eu = from_up(E), Ed = from_down(E);
+      const uint64_t e_r = E >> 1, e_l = E << 1;  // cell to the right / left is empty
+      fA = A & e_r;
+      fB = B & e_l;
+      const uint64_t bA = A & ~e_r, bB = B & ~e_l;  // forward cell blocked
+      // blocked agents' empty side candidates: 0 FD-, 1 FD+, 2 L-, 3 L+
+      const uint64_t oA0 = bA & (Eu >> 1), oA1 = bA & (Ed >> 1);
+      const uint64_t oB0 = bB & (Eu << 1), oB1 = bB & (Ed << 1);
+      const uint64_t o2 = (bA | bB) & Eu, o3 = (bA | bB) & Ed;
+      const uint64_t o0 = oA0 | oB0, o1 = oA1 | oB1;
+      const uint64_t multi = (o0 & (o1 | o2 | o3)) | (o1 & (o2 | o3)) | (o2 & o3);
+      const uint64_t single = (o0 | o1 | o2 | o3) & ~multi;
+      // side requests by requester row: 0 FD-A, 1 FD-B, 2 FD+A, 3 FD+B, 4 L-, 5 L+
+      rq[0] = single & oA0;
+      rq[1] = single & oB0;
+      rq[2] = single & oA1;
+      rq[3] = single & oB1;
+      rq[4] = single & o2;
+      rq[5] = single & o3;
+      // possible requesters of each cell, by direction; two or more: contestable
+      const uint64_t P[8] = {fA << 1,           fB >> 1,           from_down(oA0) << 1, from_up(oA1) << 1,
+                             from_down(oB0) >> 1, from_up(oB1) >> 1, from_down(o2),       from_up(o3)};
+      uint64_t ones = 0ull, twos = 0ull;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        twos |= ones & P[q];
+        ones |= P[q];
+      }
+      const uint64_t pu = from_up(twos), pd = from_down(twos);
+      const uint64_t need = (fA & (twos >> 1)) | (fB & (twos << 1)) | (oA0 & (pu >> 1)) | (oA1 & (pd >> 1)) |
+                            (oB0 & (pu << 1)) | (oB1 & (pd << 1)) | (o2 & pu) | (o3 & pd);
+      if (row_lane) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) side[q * R + lane] = 0ull;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cwin[q * R + lane] = 0ull;
+      }
+      const int nq = enqueue_row_bits(queue, multi | need, lane);
+      if (lane == 0) ctl[0] = (uint32_t)nq;
+    }
+    __syncthreads();
+
+    // ---- 2. draw: tickets for all queued agents, choices where needed -----
+    const int nq = (int)ctl[0];
+    if (nq > 0) {
+      for (int qi = tid; qi < nq; qi += nthreads) {
+        const uint32_t e = queue[qi];
+        const int r = (int)(e & 63u), c = (int)((e >> 6) & 63u);
+        const bool is_a = (H(s, 0, r) >> c) & 1ull;
+        const int d = is_a ? 1 : -1;
+        auto empty_at = [&](int rr, int cc) -> bool {
+          if (rr < 0 || rr >= R || cc < 0 || cc >= 64) return false;
+          return !(((H(s, 0, rr) | H(s, 1, rr) | wall_m[rr]) >> cc) & 1ull);
+        };
+        const bool fwd = empty_at(r, c + d);
+        const unsigned avail = (unsigned)empty_at(r - 1, c + d) | ((unsigned)empty_at(r + 1, c + d) << 1) |
+                               ((unsigned)empty_at(r - 1, c) << 2) | ((unsigned)empty_at(r + 1, c) << 3);
+        const Words w = agent_words(ids[r * 64 + c] - 1u, t, S.key0, S.key1);
+        tick[r * 64 + c] = w.w0;
+        if (!fwd && (avail & (avail - 1u)) != 0u) {  // two or more side candidates: a choice
+          int req;
+          if (MODE == 0) {
+            req = lem_choose(avail, w.w1, w.w2);
+          } else {
+            const int gp = is_a ? 0 : 1;
+            const float* tp = is_a ? tau_a : tau_b;
+            float tau[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              tau[j] = 0.0f;
+              if ((avail >> j) & 1u) {
+                const int rr = r + ((j & 1) ? 1 : -1);
+                const int cc = c + (j < 2 ? d : 0);
+                float v = tp[rr * 64 + cc];
+                for (int u = 1; u <= s; ++u) {  // the cell's value at step s
+                  v = S.keep * v;
+                  if ((H(u, gp, rr) >> cc) & 1ull) v = v + S.dtau;
+                }
+                tau[j] = v;
+              }
+            }
+            req = aco_choose(avail, tau, S.alpha, S.eta_diag, S.eta_lat, w.w1, w.w2);
+          }
+          const int which = req == kReqFDm ? (is_a ? 0 : 1)
+                                           : (req == kReqFDp ? (is_a ? 2 : 3) : (req == kReqLm ? 4 : 5));
+          atomicOr((unsigned long long*)&side[which * R + r], 1ull << c);
+        }
+      }
+      __syncthreads();
+    }
+
+    // ---- 3. gather: requesters of every cell, by direction -----------------
+    if (mask_wave) {
+      uint64_t own[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) own[q] = rq[q] | ((nq > 0 && row_lane) ? side[q * R + lane] : 0ull);
+      Wt[0] = fA << 1;                 // A from the left (F)
+      Wt[1] = fB >> 1;                 // B from the right (F)
+      Wt[2] = from_down(own[0]) << 1;  // A from below-left (FD-)
+      Wt[3] = from_up(own[2]) << 1;    // A from above-left (FD+)
+      Wt[4] = from_down(own[1]) >> 1;  // B from below-right (FD-)
+      Wt[5] = from_up(own[3]) >> 1;    // B from above-right (FD+)
+      Wt[6] = from_down(own[4]);       // from below (L-)
+      Wt[7] = from_up(own[5]);         // from above (L+)
+      uint64_t ones = 0ull, twos = 0ull;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        twos |= ones & Wt[q];
+        ones |= Wt[q];
+      }
+      if (row_lane) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) reqm[q * R + lane] = Wt[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) Wt[q] &= ~twos;  // uncontested winners
+      const int na = enqueue_row_bits(queue, ones, lane);
+      if (lane == 0) ctl[1] = (uint32_t)na;
+    }
+    __syncthreads();
+
+    // ---- 4. resolve contests; every winner's id moves to its target --------
+    const int na = (int)ctl[1];
+    if (na > 0) {
+      for (int qi = tid; qi < na; qi += nthreads) {
+        const uint32_t e = queue[qi];
+        const int r = (int)(e & 63u), c = (int)((e >> 6) & 63u);
+        uint32_t dirs = 0u;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) dirs |= (uint32_t)((reqm[q * R + r] >> c) & 1ull) << q;
+        int best = __ffs(dirs) - 1;
+        uint32_t src_id = ids[(r + dir_dr(best)) * 64 + c + dir_dc(best)];
+        if (dirs & (dirs - 1u)) {  // contested: lowest (ticket, agent number)
+          uint32_t best_t = tick[(r + dir_dr(best)) * 64 + c + dir_dc(best)];
+          uint32_t rest = dirs & (dirs - 1u);
+          while (rest) {
+            const int q = __ffs(rest) - 1;
+            rest &= rest - 1u;
+            const int si = (r + dir_dr(q)) * 64 + c + dir_dc(q);
+            const uint32_t tk = tick[si], k = ids[si];
+            if (tk < best_t || (tk == best_t && k < src_id)) {
+              best = q;
+              best_t = tk;
+              src_id = k;
+            }
+          }
+          atomicOr((unsigned long long*)&cwin[best * R + r], 1ull << c);
+        }
+        ids[r * 64 + c] = src_id;
+      }
+      __syncthreads();
+    }
+
+    // ---- 5. commit: next occupancy, recorded in the history ---------------
+    if (mask_wave) {
+      if (na > 0 && row_lane) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Wt[q] |= cwin[q * R + lane];
+      }
+      const uint64_t in_a = Wt[0] | Wt[2] | Wt[3] | (Wt[6] & from_down(A)) | (Wt[7] & from_up(A));
+      const uint64_t in_b = Wt[1] | Wt[4] | Wt[5] | (Wt[6] & from_down(B)) | (Wt[7] & from_up(B));
+      const uint64_t out = (Wt[0] >> 1) | (Wt[1] << 1) | (from_up(Wt[2]) >> 1) | (from_down(Wt[3]) >> 1) |
+                           (from_up(Wt[4]) << 1) | (from_down(Wt[5]) << 1) | from_up(Wt[6]) | from_down(Wt[7]);
+      A = (A & ~out) | in_a;
+      B = (B & ~out) | in_b;
+      moved_in = in_a | in_b;
+      if (row_lane) {
+        H(s + 1, 0, lane) = A;
+        H(s + 1, 1, lane) = B;
+      }
+    }
+  }
+  if (mask_wave && row_lane) moved_m[lane] = moved_in;
+  __syncthreads();
+
+  // ---- write the interior back; pheromone applied step by step ------------
+  uint32_t cnt[kTileStatFields] = {0, 0, 0, 0, 0};
+  for (int r = h + wave; r < R - h; r += nwaves) {
+    const int gy = y0 + r;
+    const int c = lane;
+    const int gx = x0 + c;
+    const bool interior = c >= h && c < h + S.IX && gx < S.W && gy < S.H;
+    const uint64_t ra = H(steps, 0, r), rb = H(steps, 1, r), rw = wall_m[r];
+    const int g = !interior ? kEmpty
+                            : ((ra & lane_bit) ? kGroupA
+                                               : ((rb & lane_bit) ? kGroupB : ((rw & lane_bit) ? kWall : kEmpty)));
+    if (interior) {
+      const size_t gi = (size_t)gy * S.W + gx;
+      S.code_out[gi] = (uint8_t)g;
+      S.id_out[gi] = (g == kGroupA || g == kGroupB) ? ids[r * 64 + c] : 0u;
+      if (MODE == 1) {
+        float va = tau_a[r * 64 + c], vb = tau_b[r * 64 + c];
+        for (int u = 1; u <= steps; ++u) {
+          va = S.keep * va;
+          vb = S.keep * vb;
+          if ((H(u, 0, r) >> c) & 1ull) va = va + S.dtau;
+          if ((H(u, 1, r) >> c) & 1ull) vb = vb + S.dtau;
+        }
+        S.tau_out[gi] = va;
+        S.tau_out[plane + gi] = vb;
+      }
+    }
+    if (last) {
+      const bool moved = interior && steps > 0 && ((moved_m[r] >> c) & 1ull);
+      cnt[0] += __popcll(__ballot(g == kGroupA));
+      cnt[1] += __popcll(__ballot(g == kGroupB));
+      cnt[2] += __popcll(__ballot(g == kGroupA && gx >= S.W - S.cross_b));
+      cnt[3] += __popcll(__ballot(g == kGroupB && gx < S.cross_a));
+      cnt[4] += __popcll(__ballot(moved));
+    }
+  }
+  if (last) {
+    if (lane == 0) {
+#pragma unroll
+      for (int f = 0; f < kTileStatFields; ++f) atomicAdd(&ctl[8 + f], cnt[f]);
+    }
+    __syncthreads();
+    if (tid < kTileStatFields) S.tile_stats[(size_t)tile_index * kTileStatFields + tid] = ctl[8 + tid];
+  }
+}
+
+}  // namespace pedsim

@@ -41,9 +41,16 @@ def assert_same(sim, st, what=""):
     assert s["step"] == st.t
 
 
-def run_both(pedsim, scn, mode, steps, chunks=(1,)):
+# One explicit tiling per engine (nw, rows, steps per launch, threads): the
+# multi-wave engine and the row-lane engine.
+ENGINES = {"multi": (1, 32, 2, 512), "rows": (0, 48, 2, 256)}
+
+
+def run_both(pedsim, scn, mode, steps, chunks=(1,), tiling=None):
     """Advance GPU and oracle together, comparing after each chunk."""
     sim = pedsim.Sim(scn)
+    if tiling is not None:
+        sim.set_tiling(mode, *tiling)
     st = oracle.State.from_scenario(scn)
     done = 0
     for c in chunks:
@@ -64,12 +71,13 @@ def run_both(pedsim, scn, mode, steps, chunks=(1,)):
 
 
 @pytest.mark.parametrize("mode", [S.MODE_LEM, S.MODE_ACO])
-def test_lem_200x100_full_run(pedsim, mode):
+@pytest.mark.parametrize("engine", sorted(ENGINES))
+def test_lem_200x100_full_run(pedsim, mode, engine):
     scn = S.lem_200x100()
     scn = S.make_scenario(200, 100, 1000, 1000, band_a=10, seed=1, mode=mode, steps=500,
                           with_tau=True)
-    say("200x100", mode)
-    run_both(pedsim, scn, mode, 500, chunks=(1, 1, 1, 2, 5, 10, 30, 50, 100))
+    say("200x100", mode, engine)
+    run_both(pedsim, scn, mode, 500, chunks=(1, 1, 1, 2, 5, 10, 30, 50, 100), tiling=ENGINES[engine])
 
 
 @pytest.mark.parametrize("W,H,na,nb,obst,seed", [
@@ -80,38 +88,42 @@ def test_lem_200x100_full_run(pedsim, mode):
     (64, 8, 0, 0, 0.0, 15),        # no agents at all
 ])
 @pytest.mark.parametrize("mode", [S.MODE_LEM, S.MODE_ACO])
-def test_ragged_grids(pedsim, W, H, na, nb, obst, seed, mode):
+@pytest.mark.parametrize("engine", sorted(ENGINES))
+def test_ragged_grids(pedsim, W, H, na, nb, obst, seed, mode, engine):
     band = max(1, min(W // 2, 6))
     scn = S.make_scenario(W, H, na, nb, band_a=band, seed=seed, mode=mode,
                           obstacle_frac=obst, with_tau=True)
-    say("ragged", W, H, mode)
-    run_both(pedsim, scn, mode, 60, chunks=(1, 1, 3, 10))
+    say("ragged", W, H, mode, engine)
+    run_both(pedsim, scn, mode, 60, chunks=(1, 1, 3, 10), tiling=ENGINES[engine])
 
 
-def test_full_grid_nobody_moves(pedsim):
+@pytest.mark.parametrize("engine", sorted(ENGINES))
+def test_full_grid_nobody_moves(pedsim, engine):
     code = S.wall_frame(70, 11)
     code[1:10, :35] = S.GROUP_A
     code[1:10, 35:] = S.GROUP_B
     scn = S.from_grid(code, seed=4, tau=np.ones((2, 11, 70), np.float32), mode=S.MODE_ACO)
     say("full grid")
-    run_both(pedsim, scn, S.MODE_ACO, 5, chunks=(1,))
+    run_both(pedsim, scn, S.MODE_ACO, 5, chunks=(1,), tiling=ENGINES[engine])
 
 
 @pytest.mark.parametrize("alpha,beta,rho,dtau", [(2, 3, 0.05, 0.5), (0, 1, 1.0, 2.0),
                                                  (3, 0, 0.3, 0.0)])
-def test_aco_parameters(pedsim, alpha, beta, rho, dtau):
+@pytest.mark.parametrize("engine", sorted(ENGINES))
+def test_aco_parameters(pedsim, alpha, beta, rho, dtau, engine):
     scn = S.make_scenario(150, 60, 700, 650, band_a=8, seed=21, mode=S.MODE_ACO,
                           obstacle_frac=0.04, alpha=alpha, beta=beta, rho=rho, dtau=dtau)
     say("aco params", alpha, beta, rho, dtau)
-    run_both(pedsim, scn, S.MODE_ACO, 120, chunks=(1, 10, 40))
+    run_both(pedsim, scn, S.MODE_ACO, 120, chunks=(1, 10, 40), tiling=ENGINES[engine])
 
 
-def test_aco_subnormal_phase(pedsim):
+@pytest.mark.parametrize("engine", sorted(ENGINES))
+def test_aco_subnormal_phase(pedsim, engine):
     """Run through the steps where unvisited cells reach the subnormal range
     and settle at the smallest fixed point (flush-to-zero would differ)."""
     scn = S.make_scenario(96, 24, 60, 60, band_a=4, seed=5, mode=S.MODE_ACO)
     say("subnormal phase")
-    run_both(pedsim, scn, S.MODE_ACO, 1000, chunks=(500, 330, 100))
+    run_both(pedsim, scn, S.MODE_ACO, 1000, chunks=(500, 330, 100), tiling=ENGINES[engine])
     sim = pedsim.Sim(scn)
     sim.step(1000)
     _, _, tau = sim.state()
@@ -138,22 +150,24 @@ def _mosaic_all_small_grids(max_agents):
 
 
 @pytest.mark.parametrize("mode", [S.MODE_LEM, S.MODE_ACO])
-def test_bruteforce_all_4x4_grids_up_to_5_agents(pedsim, mode):
+@pytest.mark.parametrize("engine", sorted(ENGINES))
+def test_bruteforce_all_4x4_grids_up_to_5_agents(pedsim, mode, engine):
     code, n = _mosaic_all_small_grids(5)
     assert n == 173889
     H, W = code.shape
     rng = np.random.default_rng(9)
     tau = rng.uniform(0.0, 2.0, size=(2, H, W)).astype(np.float32)
     scn = S.from_grid(code, seed=77, tau=tau, mode=mode)
-    say("bruteforce", mode, W, H)
-    run_both(pedsim, scn, mode, 3, chunks=(1, 1, 1))
+    say("bruteforce", mode, W, H, engine)
+    run_both(pedsim, scn, mode, 3, chunks=(1, 1, 1), tiling=ENGINES[engine])
 
 
-def test_aco_1024x512_full_run(pedsim):
+@pytest.mark.parametrize("tiling", [None, ENGINES["rows"]])
+def test_aco_1024x512_full_run(pedsim, tiling):
     """The 100K-agent ACO workload over all 2,000 steps."""
     scn = S.aco_1024x512()
-    say("aco 1024x512 x2000")
-    run_both(pedsim, scn, S.MODE_ACO, 2000, chunks=(1, 1, 8, 90, 400))
+    say("aco 1024x512 x2000", tiling)
+    run_both(pedsim, scn, S.MODE_ACO, 2000, chunks=(1, 1, 8, 90, 400), tiling=tiling)
 
 
 @pytest.mark.parametrize("mode", [S.MODE_LEM, S.MODE_ACO])
@@ -252,9 +266,10 @@ def test_aco_without_pheromone_refused(pedsim):
 
 
 TILINGS = [(1, 32, 1, 256), (1, 48, 2, 512), (1, 64, 3, 1024), (2, 64, 2, 1024), (2, 64, 4, 1024),
-           (1, 96, 2, 128),
-           # one-wave engine (64-lane workgroups)
-           (1, 32, 1, 64), (1, 48, 2, 64), (1, 64, 3, 64), (1, 64, 1, 64)]
+           (1, 96, 2, 128), (1, 32, 1, 64),
+           # row-lane engine: regions of 64 columns, at most 64 rows
+           (0, 64, 1, 64), (0, 32, 1, 128), (0, 48, 2, 256), (0, 64, 3, 256), (0, 64, 2, 512),
+           (0, 40, 4, 1024), (0, 64, 8, 256)]
 
 
 @pytest.mark.parametrize("mode", [S.MODE_LEM, S.MODE_ACO])
