@@ -10,6 +10,58 @@
 
 namespace pedsim {
 
+// readfirstlane returns a signed int: widen through uint32_t so that the low
+// word is not sign-extended into the high one.
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  return ((uint64_t)uniform_u32((uint32_t)(v >> 32)) << 32) | (uint64_t)uniform_u32((uint32_t)v);
+}
+
+// A workgroup-uniform copy of a scenario read from global memory: every word
+// goes through readfirstlane, so the copy (and everything derived from it)
+// lives in scalar registers.
+__device__ __forceinline__ Scenario uniform_scenario(const Scenario* src) {
+  static_assert(sizeof(Scenario) % 4 == 0, "Scenario must be a whole number of words");
+  Scenario out;
+  const uint32_t* w = (const uint32_t*)src;
+  uint32_t* o = (uint32_t*)&out;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(Scenario) / 4); ++i) o[i] = uniform_u32(w[i]);
+  return out;
+}
+
+// The work item's scenario for launch j, with the planes it reads and writes.
+struct ItemView {
+  Scenario S;
+  uint64_t t0;
+  int steps, mode, tile;
+  bool last;
+};
+
+__device__ __forceinline__ ItemView item_view(const BatchPlan& P, const BatchEntry* E, int lo, int item, int j) {
+  ItemView v;
+  const int slot = __builtin_amdgcn_readfirstlane(E[lo].slot);
+  const int first = __builtin_amdgcn_readfirstlane(E[lo].first);
+  const BatchSlot& B = P.slots[slot];
+  v.S = uniform_scenario(&B.S);
+  const int par = j & 1;
+  v.S.code_in = (const uint8_t*)uniform_u64((uint64_t)B.code[par]);
+  v.S.id_in = (const uint32_t*)uniform_u64((uint64_t)B.id[par]);
+  v.S.tau_in = (const float*)uniform_u64((uint64_t)B.tau[par]);
+  v.S.code_out = (uint8_t*)uniform_u64((uint64_t)B.code[par ^ 1]);
+  v.S.id_out = (uint32_t*)uniform_u64((uint64_t)B.id[par ^ 1]);
+  v.S.tau_out = (float*)uniform_u64((uint64_t)B.tau[par ^ 1]);
+  const int bsteps = __builtin_amdgcn_readfirstlane(B.steps);
+  v.mode = __builtin_amdgcn_readfirstlane(B.mode);
+  const int done = j * P.k;
+  v.steps = bsteps - done < P.k ? bsteps - done : P.k;
+  v.last = done + v.steps == bsteps;
+  v.t0 = uniform_u64(B.t0) + (uint64_t)done;
+  v.tile = item - first;
+  return v;
+}
+
 template <int NW>
 __global__ __launch_bounds__(1024) void batch_kernel(BatchPlan P, int j) {
   extern __shared__ __align__(16) uint8_t smem[];
@@ -29,29 +81,17 @@ __global__ __launch_bounds__(1024) void batch_kernel(BatchPlan P, int j) {
       const int mid = (lo + hi + 1) >> 1;
       if (E[mid].first <= item) lo = mid; else hi = mid - 1;
     }
-    const BatchSlot& B = P.slots[E[lo].slot];
-    Scenario S = B.S;
-    const int par = j & 1;
-    S.code_in = B.code[par];
-    S.id_in = B.id[par];
-    S.tau_in = B.tau[par];
-    S.code_out = B.code[par ^ 1];
-    S.id_out = B.id[par ^ 1];
-    S.tau_out = B.tau[par ^ 1];
-    const int done = j * P.k;
-    const int steps = B.steps - done < P.k ? B.steps - done : P.k;
-    const bool last = done + steps == B.steps;
-    const int tile = item - E[lo].first;
-    const int tx = tile % S.tiles_x, ty = tile / S.tiles_x;
-    if (B.mode == kModeAco)
-      advance_tile<NW, kModeAco>(S, smem, P.rows, tx, ty, tile, B.t0 + (uint64_t)done, steps, last);
+    const ItemView v = item_view(P, E, lo, item, j);
+    const int tx = v.tile % v.S.tiles_x, ty = v.tile / v.S.tiles_x;
+    if (v.mode == kModeAco)
+      advance_tile<NW, kModeAco>(v.S, smem, P.rows, tx, ty, v.tile, v.t0, v.steps, v.last);
     else
-      advance_tile<NW, kModeLem>(S, smem, P.rows, tx, ty, tile, B.t0 + (uint64_t)done, steps, last);
+      advance_tile<NW, kModeLem>(v.S, smem, P.rows, tx, ty, v.tile, v.t0, v.steps, v.last);
   }
 }
 
 // The same with the row-lane engine (regions of 64 columns).
-__global__ __launch_bounds__(1024) void batch_rows_kernel(BatchPlan P, int j) {
+__global__ __launch_bounds__(kRowsMaxThreads) void batch_rows_kernel(BatchPlan P, int j) {
   extern __shared__ __align__(16) uint8_t smem[];
   int& s_item = *(int*)(smem + RowsLayout{P.rows, P.k, true}.bytes());
   const int count = P.counts[j];
@@ -68,24 +108,12 @@ __global__ __launch_bounds__(1024) void batch_rows_kernel(BatchPlan P, int j) {
       const int mid = (lo + hi + 1) >> 1;
       if (E[mid].first <= item) lo = mid; else hi = mid - 1;
     }
-    const BatchSlot& B = P.slots[E[lo].slot];
-    Scenario S = B.S;
-    const int par = j & 1;
-    S.code_in = B.code[par];
-    S.id_in = B.id[par];
-    S.tau_in = B.tau[par];
-    S.code_out = B.code[par ^ 1];
-    S.id_out = B.id[par ^ 1];
-    S.tau_out = B.tau[par ^ 1];
-    const int done = j * P.k;
-    const int steps = B.steps - done < P.k ? B.steps - done : P.k;
-    const bool last = done + steps == B.steps;
-    const int tile = item - E[lo].first;
-    const int tx = tile % S.tiles_x, ty = tile / S.tiles_x;
-    if (B.mode == kModeAco)
-      advance_tile_rows<kModeAco>(S, smem, P.rows, P.k, tx, ty, tile, B.t0 + (uint64_t)done, steps, last);
+    const ItemView v = item_view(P, E, lo, item, j);
+    const int tx = v.tile % v.S.tiles_x, ty = v.tile / v.S.tiles_x;
+    if (v.mode == kModeAco)
+      advance_tile_rows<kModeAco>(v.S, smem, P.rows, P.k, tx, ty, v.tile, v.t0, v.steps, v.last);
     else
-      advance_tile_rows<kModeLem>(S, smem, P.rows, P.k, tx, ty, tile, B.t0 + (uint64_t)done, steps, last);
+      advance_tile_rows<kModeLem>(v.S, smem, P.rows, P.k, tx, ty, v.tile, v.t0, v.steps, v.last);
   }
 }
 

@@ -22,8 +22,8 @@ __global__ __launch_bounds__(1024) void tile_kernel(Scenario S, int R, uint64_t 
 }
 
 template <int MODE>
-__global__ __launch_bounds__(1024) void tile_rows_kernel(Scenario S, int R, int k_max, uint64_t t0, int steps,
-                                                         int last) {
+__global__ __launch_bounds__(kRowsMaxThreads) void tile_rows_kernel(Scenario S, int R, int k_max, uint64_t t0,
+                                                                    int steps, int last) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int ntiles = S.tiles_x * S.tiles_y;
   const int tile = tile_of_block(blockIdx.x, ntiles);
@@ -38,7 +38,8 @@ size_t tile_lds_bytes(const Tiling& tl, bool aco) {
 
 bool tiling_valid(const Tiling& tl, bool aco, int max_lds) {
   if (tl.nw < 0 || tl.nw > 2) return false;
-  if (rows_engine(tl) && (tl.rows > kRowsMaxRows || tl.steps > kRowsMaxSteps)) return false;
+  if (rows_engine(tl) && (tl.rows > kRowsMaxRows || tl.steps > kRowsMaxSteps || tl.threads > kRowsMaxThreads))
+    return false;
   if (tl.steps < 1 || tl.threads < 64 || tl.threads > 1024 || tl.threads % 64) return false;
   if (tl.rows < 1 || tl.rows > 1023) return false;
   if (region_cols(tl) - 6 * tl.steps < kMinInteriorX || tl.rows - 6 * tl.steps < kMinInteriorY) return false;

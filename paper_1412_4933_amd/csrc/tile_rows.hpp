@@ -43,6 +43,7 @@ namespace pedsim {
 
 constexpr int kRowsMaxRows = 64;
 constexpr int kRowsMaxSteps = 8;
+constexpr int kRowsMaxThreads = 512;  // workgroup size limit
 
 // LDS layout of a row-lane region of R rows x 64 columns, k steps per launch.
 struct RowsLayout {
@@ -57,8 +58,8 @@ struct RowsLayout {
   __host__ __device__ size_t ctl() const { return moved() + (size_t)R * 8; }             // 16 u32
   __host__ __device__ size_t ids() const { return ctl() + 64; }                         // [R][64] u32
   __host__ __device__ size_t tick() const { return ids() + (size_t)R * 256; }           // [R][64] u32
-  __host__ __device__ size_t queue() const { return tick() + (size_t)R * 256; }         // [R*64] u32
-  __host__ __device__ size_t tau() const { return queue() + (size_t)R * 256; }          // [2][R][64] f32
+  __host__ __device__ size_t queue() const { return tick() + (size_t)R * 256; }         // [R*64] u16
+  __host__ __device__ size_t tau() const { return queue() + (size_t)R * 128; }          // [2][R][64] f32
   __host__ __device__ size_t bytes() const { return tau() + (aco ? (size_t)R * 512 : 0); }
 };
 
@@ -79,10 +80,11 @@ __device__ __forceinline__ int lanes_below(uint64_t bal) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
 }
 
-// Wave 0: append (row = lane, column) of every set bit of `bits` to `queue`;
-// returns the number appended (wave-uniform). Lanes take turns bit by bit,
-// so the loop runs as many times as the fullest row has bits.
-__device__ __forceinline__ int enqueue_row_bits(uint32_t* queue, uint64_t bits, int lane) {
+// Wave 0: append (row = lane, column) of every set bit of `bits` to `queue`
+// as row | column << 6; returns the number appended (wave-uniform). Lanes
+// take turns bit by bit, so the loop runs as many times as the fullest row
+// has bits.
+__device__ __forceinline__ int enqueue_row_bits(uint16_t* queue, uint64_t bits, int lane) {
   int base = 0;
   for (;;) {
     const bool has = bits != 0ull;
@@ -91,11 +93,42 @@ __device__ __forceinline__ int enqueue_row_bits(uint32_t* queue, uint64_t bits, 
     if (has) {
       const int c = __ffsll((unsigned long long)bits) - 1;
       bits &= bits - 1ull;
-      queue[base + lanes_below(bal)] = (uint32_t)lane | ((uint32_t)c << 6);
+      queue[base + lanes_below(bal)] = (uint16_t)(lane | (c << 6));
     }
     base += __popcll(bal);
   }
   return base;
+}
+
+// Staging: a thread loads the cells of column `lane` in rows wave + j * nwaves
+// (j < kStageRows per batch) into registers, all loads in flight together,
+// then converts them into the region's LDS form.
+constexpr int kStageRows = 8;
+
+struct StageRegs {
+  int g[kStageRows];
+  uint32_t id[kStageRows];
+  float ta[kStageRows], tb[kStageRows];
+};
+
+// Rows row0 + j * nwaves (j < kStageRows) of the region at (x0, y0).
+template <int MODE>
+__device__ __forceinline__ void stage_issue(const Scenario& S, int R, int x0, int y0, int row0, int nwaves, int lane,
+                                            StageRegs& q) {
+  const size_t plane = (size_t)S.W * (size_t)S.H;
+#pragma unroll
+  for (int j = 0; j < kStageRows; ++j) {
+    const int r = row0 + j * nwaves;
+    const int gx = x0 + lane, gy = y0 + r;
+    const bool in = r < R && gx >= 0 && gx < S.W && gy >= 0 && gy < S.H;
+    const size_t gi = in ? (size_t)gy * S.W + gx : 0;
+    q.g[j] = in ? S.code_in[gi] : kWall;
+    q.id[j] = in ? S.id_in[gi] : 0u;
+    if (MODE == 1) {
+      q.ta[j] = in ? S.tau_in[gi] : 0.0f;
+      q.tb[j] = in ? S.tau_in[plane + gi] : 0.0f;
+    }
+  }
 }
 
 template <int MODE>
@@ -111,7 +144,7 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
   uint32_t* ctl = (uint32_t*)(smem + L.ctl());
   uint32_t* ids = (uint32_t*)(smem + L.ids());
   uint32_t* tick = (uint32_t*)(smem + L.tick());
-  uint32_t* queue = (uint32_t*)(smem + L.queue());
+  uint16_t* queue = (uint16_t*)(smem + L.queue());
   float* tau_a = (float*)(smem + L.tau());
   float* tau_b = tau_a + (size_t)R * 64;
   // occupancy of group g (0 = A, 1 = B) at step s of the launch, row r
@@ -130,39 +163,25 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
   const size_t plane = (size_t)S.W * (size_t)S.H;
   const uint64_t lane_bit = 1ull << lane;
 
-  // ---- stage: all loads of a wave's rows in flight together ---------------
-  constexpr int kStageRows = 8;
-  for (int r0 = wave * kStageRows; r0 < R; r0 += nwaves * kStageRows) {
-    int g[kStageRows];
-    uint32_t idv[kStageRows];
-    float ta[kStageRows], tb[kStageRows];
+  // ---- stage: rows dealt round-robin to the waves, all loads in flight --
+  for (int r0 = wave; r0 < R; r0 += nwaves * kStageRows) {
+    StageRegs q;
+    stage_issue<MODE>(S, R, x0, y0, r0, nwaves, lane, q);
 #pragma unroll
     for (int j = 0; j < kStageRows; ++j) {
-      const int gx = x0 + lane, gy = y0 + r0 + j;
-      const bool in = r0 + j < R && gx >= 0 && gx < S.W && gy >= 0 && gy < S.H;
-      const size_t gi = in ? (size_t)gy * S.W + gx : 0;
-      g[j] = in ? S.code_in[gi] : kWall;
-      idv[j] = in ? S.id_in[gi] : 0u;
-      if (MODE == 1) {
-        ta[j] = in ? S.tau_in[gi] : 0.0f;
-        tb[j] = in ? S.tau_in[plane + gi] : 0.0f;
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < kStageRows; ++j) {
-      const int r = r0 + j;
+      const int r = r0 + j * nwaves;
       if (r >= R) break;
-      const uint64_t ba = __ballot(g[j] == kGroupA), bb = __ballot(g[j] == kGroupB);
-      const uint64_t bw = __ballot(g[j] == kWall);
+      const uint64_t ba = __ballot(q.g[j] == kGroupA), bb = __ballot(q.g[j] == kGroupB);
+      const uint64_t bw = __ballot(q.g[j] == kWall);
       if (lane == 0) {
         H(0, 0, r) = ba;
         H(0, 1, r) = bb;
         wall_m[r] = bw;
       }
-      ids[r * 64 + lane] = idv[j];
+      ids[r * 64 + lane] = q.id[j];
       if (MODE == 1) {
-        tau_a[r * 64 + lane] = ta[j];
-        tau_b[r * 64 + lane] = tb[j];
+        tau_a[r * 64 + lane] = q.ta[j];
+        tau_b[r * 64 + lane] = q.tb[j];
       }
     }
   }
@@ -363,39 +382,72 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
   __syncthreads();
 
   // ---- write the interior back; pheromone applied step by step ------------
+  // Each wave takes blocks of kWriteRows consecutive rows and issues every
+  // LDS read of a block before the arithmetic; the occupancy history of a
+  // lane's cell is gathered into bit vectors (bit u: occupied after step u).
+  constexpr int kWriteRows = 4;
   uint32_t cnt[kTileStatFields] = {0, 0, 0, 0, 0};
-  for (int r = h + wave; r < R - h; r += nwaves) {
-    const int gy = y0 + r;
+  for (int r0 = h + wave * kWriteRows; r0 < R - h; r0 += nwaves * kWriteRows) {
     const int c = lane;
     const int gx = x0 + c;
-    const bool interior = c >= h && c < h + S.IX && gx < S.W && gy < S.H;
-    const uint64_t ra = H(steps, 0, r), rb = H(steps, 1, r), rw = wall_m[r];
-    const int g = !interior ? kEmpty
-                            : ((ra & lane_bit) ? kGroupA
-                                               : ((rb & lane_bit) ? kGroupB : ((rw & lane_bit) ? kWall : kEmpty)));
-    if (interior) {
-      const size_t gi = (size_t)gy * S.W + gx;
-      S.code_out[gi] = (uint8_t)g;
-      S.id_out[gi] = (g == kGroupA || g == kGroupB) ? ids[r * 64 + c] : 0u;
+    uint64_t ra[kWriteRows], rb[kWriteRows], rw[kWriteRows], rm[kWriteRows];
+    uint32_t idv[kWriteRows], hist_a[kWriteRows], hist_b[kWriteRows];
+    float va[kWriteRows], vb[kWriteRows];
+#pragma unroll
+    for (int j = 0; j < kWriteRows; ++j) {
+      const int r = r0 + j < R - h ? r0 + j : R - h - 1;  // rows past the interior repeat the last one, unused
+      ra[j] = H(steps, 0, r);
+      rb[j] = H(steps, 1, r);
+      rw[j] = wall_m[r];
+      rm[j] = moved_m[r];
+      idv[j] = ids[r * 64 + c];
+      hist_a[j] = 0u;
+      hist_b[j] = 0u;
       if (MODE == 1) {
-        float va = tau_a[r * 64 + c], vb = tau_b[r * 64 + c];
-        for (int u = 1; u <= steps; ++u) {
-          va = S.keep * va;
-          vb = S.keep * vb;
-          if ((H(u, 0, r) >> c) & 1ull) va = va + S.dtau;
-          if ((H(u, 1, r) >> c) & 1ull) vb = vb + S.dtau;
+        va[j] = tau_a[r * 64 + c];
+        vb[j] = tau_b[r * 64 + c];
+#pragma unroll
+        for (int u = 1; u <= kRowsMaxSteps; ++u) {
+          if (u <= steps) {
+            hist_a[j] |= (uint32_t)((H(u, 0, r) >> c) & 1ull) << u;
+            hist_b[j] |= (uint32_t)((H(u, 1, r) >> c) & 1ull) << u;
+          }
         }
-        S.tau_out[gi] = va;
-        S.tau_out[plane + gi] = vb;
       }
     }
-    if (last) {
-      const bool moved = interior && steps > 0 && ((moved_m[r] >> c) & 1ull);
-      cnt[0] += __popcll(__ballot(g == kGroupA));
-      cnt[1] += __popcll(__ballot(g == kGroupB));
-      cnt[2] += __popcll(__ballot(g == kGroupA && gx >= S.W - S.cross_b));
-      cnt[3] += __popcll(__ballot(g == kGroupB && gx < S.cross_a));
-      cnt[4] += __popcll(__ballot(moved));
+#pragma unroll
+    for (int j = 0; j < kWriteRows; ++j) {
+      const int r = r0 + j;
+      if (r >= R - h) break;  // wave-uniform
+      const int gy = y0 + r;
+      const bool interior = c >= h && c < h + S.IX && gx < S.W && gy < S.H;
+      const uint64_t lb = lane_bit;
+      const int g = !interior ? kEmpty
+                              : ((ra[j] & lb) ? kGroupA : ((rb[j] & lb) ? kGroupB : ((rw[j] & lb) ? kWall : kEmpty)));
+      if (interior) {
+        const size_t gi = (size_t)gy * S.W + gx;
+        S.code_out[gi] = (uint8_t)g;
+        S.id_out[gi] = (g == kGroupA || g == kGroupB) ? idv[j] : 0u;
+        if (MODE == 1) {
+          float a = va[j], b = vb[j];
+          for (int u = 1; u <= steps; ++u) {
+            a = S.keep * a;
+            b = S.keep * b;
+            if ((hist_a[j] >> u) & 1u) a = a + S.dtau;
+            if ((hist_b[j] >> u) & 1u) b = b + S.dtau;
+          }
+          S.tau_out[gi] = a;
+          S.tau_out[plane + gi] = b;
+        }
+      }
+      if (last) {
+        const bool moved = interior && steps > 0 && ((rm[j] >> c) & 1ull);
+        cnt[0] += __popcll(__ballot(g == kGroupA));
+        cnt[1] += __popcll(__ballot(g == kGroupB));
+        cnt[2] += __popcll(__ballot(g == kGroupA && gx >= S.W - S.cross_b));
+        cnt[3] += __popcll(__ballot(g == kGroupB && gx < S.cross_a));
+        cnt[4] += __popcll(__ballot(moved));
+      }
     }
   }
   if (last) {

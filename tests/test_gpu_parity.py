@@ -269,7 +269,7 @@ TILINGS = [(1, 32, 1, 256), (1, 48, 2, 512), (1, 64, 3, 1024), (2, 64, 2, 1024),
            (1, 96, 2, 128), (1, 32, 1, 64),
            # row-lane engine: regions of 64 columns, at most 64 rows
            (0, 64, 1, 64), (0, 32, 1, 128), (0, 48, 2, 256), (0, 64, 3, 256), (0, 64, 2, 512),
-           (0, 40, 4, 1024), (0, 64, 8, 256)]
+           (0, 40, 4, 512), (0, 64, 8, 256)]
 
 
 @pytest.mark.parametrize("mode", [S.MODE_LEM, S.MODE_ACO])
