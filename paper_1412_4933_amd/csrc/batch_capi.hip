@@ -90,7 +90,7 @@ struct sim_batch {
 namespace {
 
 Tiling default_batch_tiling() {
-  static const Tiling opts[] = {{1, 64, 2, 512}, {1, 32, 2, 512}, {1, 32, 1, 256}};
+  static const Tiling opts[] = {{0, 48, 3, 512}, {1, 64, 2, 512}, {1, 32, 1, 256}};
   for (const Tiling& t : opts)
     if (tiling_valid(t, true, max_dynamic_lds() - kBatchItemBytes)) return t;
   return opts[2];

@@ -91,7 +91,7 @@ __global__ __launch_bounds__(1024) void batch_kernel(BatchPlan P, int j) {
 }
 
 // The same with the row-lane engine (regions of 64 columns).
-__global__ __launch_bounds__(kRowsMaxThreads) void batch_rows_kernel(BatchPlan P, int j) {
+__global__ __launch_bounds__(kRowsMaxThreads, kRowsMinWavesPerSimd) void batch_rows_kernel(BatchPlan P, int j) {
   extern __shared__ __align__(16) uint8_t smem[];
   int& s_item = *(int*)(smem + RowsLayout{P.rows, P.k, true}.bytes());
   const int count = P.counts[j];

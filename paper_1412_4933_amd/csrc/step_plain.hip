@@ -22,7 +22,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(Scenario S, int R, uint64_t 
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kRowsMaxThreads) void tile_rows_kernel(Scenario S, int R, int k_max, uint64_t t0,
+__global__ __launch_bounds__(kRowsMaxThreads, kRowsMinWavesPerSimd) void tile_rows_kernel(Scenario S, int R, int k_max, uint64_t t0,
                                                                     int steps, int last) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int ntiles = S.tiles_x * S.tiles_y;

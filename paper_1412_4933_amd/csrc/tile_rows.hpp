@@ -44,6 +44,9 @@ namespace pedsim {
 constexpr int kRowsMaxRows = 64;
 constexpr int kRowsMaxSteps = 8;
 constexpr int kRowsMaxThreads = 512;  // workgroup size limit
+// Register budget: at least 4 waves per SIMD (<= 128 VGPRs), so that two
+// 512-thread workgroups share a compute unit.
+constexpr int kRowsMinWavesPerSimd = 4;
 
 // LDS layout of a row-lane region of R rows x 64 columns, k steps per launch.
 struct RowsLayout {
@@ -254,16 +257,26 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
       for (int qi = tid; qi < nq; qi += nthreads) {
         const uint32_t e = queue[qi];
         const int r = (int)(e & 63u), c = (int)((e >> 6) & 63u);
-        const bool is_a = (H(s, 0, r) >> c) & 1ull;
+        // One round of LDS reads: rows r-1, r, r+1 (clamped; rows outside the
+        // region count as wall) and the agent's id.
+        const int ru = r > 0 ? r - 1 : r, rd = r + 1 < R ? r + 1 : r;
+        const uint64_t a0 = H(s, 0, r), b0 = H(s, 1, r), w0m = wall_m[r];
+        const uint64_t au = H(s, 0, ru), bu = H(s, 1, ru), wu = wall_m[ru];
+        const uint64_t ad = H(s, 0, rd), bd = H(s, 1, rd), wd = wall_m[rd];
+        const uint32_t id = ids[r * 64 + c];
+        const uint64_t e0 = ~(a0 | b0 | w0m);
+        const uint64_t eu = r > 0 ? ~(au | bu | wu) : 0ull;
+        const uint64_t ed = r + 1 < R ? ~(ad | bd | wd) : 0ull;
+        const bool is_a = (a0 >> c) & 1ull;
         const int d = is_a ? 1 : -1;
-        auto empty_at = [&](int rr, int cc) -> bool {
-          if (rr < 0 || rr >= R || cc < 0 || cc >= 64) return false;
-          return !(((H(s, 0, rr) | H(s, 1, rr) | wall_m[rr]) >> cc) & 1ull);
-        };
-        const bool fwd = empty_at(r, c + d);
-        const unsigned avail = (unsigned)empty_at(r - 1, c + d) | ((unsigned)empty_at(r + 1, c + d) << 1) |
-                               ((unsigned)empty_at(r - 1, c) << 2) | ((unsigned)empty_at(r + 1, c) << 3);
-        const Words w = agent_words(ids[r * 64 + c] - 1u, t, S.key0, S.key1);
+        const int cf = c + d;  // forward column; outside the region when -1 or 64
+        const bool cf_in = cf >= 0 && cf < 64;
+        const int cfc = cf_in ? cf : c;
+        const unsigned bf = cf_in ? 1u : 0u;
+        const bool fwd = bf & (unsigned)(e0 >> cfc);
+        const unsigned avail = (bf & (unsigned)(eu >> cfc)) | ((bf & (unsigned)(ed >> cfc)) << 1) |
+                               (((unsigned)(eu >> c) & 1u) << 2) | (((unsigned)(ed >> c) & 1u) << 3);
+        const Words w = agent_words(id - 1u, t, S.key0, S.key1);
         tick[r * 64 + c] = w.w0;
         if (!fwd && (avail & (avail - 1u)) != 0u) {  // two or more side candidates: a choice
           int req;
@@ -272,21 +285,23 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
           } else {
             const int gp = is_a ? 0 : 1;
             const float* tp = is_a ? tau_a : tau_b;
-            float tau[4];
+            // candidates 0 FD- (ru, cfc), 1 FD+ (rd, cfc), 2 L- (ru, c), 3 L+ (rd, c):
+            // their values at the launch start, advanced to step s with the
+            // occupancy of their two rows after each step
+            float tau[4] = {tp[ru * 64 + cfc], tp[rd * 64 + cfc], tp[ru * 64 + c], tp[rd * 64 + c]};
+            for (int u = 1; u <= s; ++u) {
+              const uint64_t hu = H(u, gp, ru), hd = H(u, gp, rd);
+              const unsigned ob = ((unsigned)(hu >> cfc) & 1u) | (((unsigned)(hd >> cfc) & 1u) << 1) |
+                                  (((unsigned)(hu >> c) & 1u) << 2) | (((unsigned)(hd >> c) & 1u) << 3);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              tau[j] = 0.0f;
-              if ((avail >> j) & 1u) {
-                const int rr = r + ((j & 1) ? 1 : -1);
-                const int cc = c + (j < 2 ? d : 0);
-                float v = tp[rr * 64 + cc];
-                for (int u = 1; u <= s; ++u) {  // the cell's value at step s
-                  v = S.keep * v;
-                  if ((H(u, gp, rr) >> cc) & 1ull) v = v + S.dtau;
-                }
-                tau[j] = v;
+              for (int j = 0; j < 4; ++j) {
+                tau[j] = S.keep * tau[j];
+                if ((ob >> j) & 1u) tau[j] = tau[j] + S.dtau;
               }
             }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (!((avail >> j) & 1u)) tau[j] = 0.0f;
             req = aco_choose(avail, tau, S.alpha, S.eta_diag, S.eta_lat, w.w1, w.w2);
           }
           const int which = req == kReqFDm ? (is_a ? 0 : 1)
@@ -337,22 +352,34 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
 #pragma unroll
         for (int q = 0; q < 8; ++q) dirs |= (uint32_t)((reqm[q * R + r] >> c) & 1ull) << q;
         int best = __ffs(dirs) - 1;
-        uint32_t src_id = ids[(r + dir_dr(best)) * 64 + c + dir_dc(best)];
+        uint32_t src_id;
         if (dirs & (dirs - 1u)) {  // contested: lowest (ticket, agent number)
-          uint32_t best_t = tick[(r + dir_dr(best)) * 64 + c + dir_dc(best)];
-          uint32_t rest = dirs & (dirs - 1u);
-          while (rest) {
-            const int q = __ffs(rest) - 1;
-            rest &= rest - 1u;
-            const int si = (r + dir_dr(q)) * 64 + c + dir_dc(q);
-            const uint32_t tk = tick[si], k = ids[si];
-            if (tk < best_t || (tk == best_t && k < src_id)) {
+          // every direction's ticket and id in one round (clamped addresses;
+          // directions without a requester are ignored)
+          uint32_t tk[8], kk[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            int sr = r + dir_dr(q), sc = c + dir_dc(q);
+            sr = sr < 0 ? 0 : (sr >= R ? R - 1 : sr);
+            sc = sc < 0 ? 0 : (sc > 63 ? 63 : sc);
+            tk[q] = tick[sr * 64 + sc];
+            kk[q] = ids[sr * 64 + sc];
+          }
+          uint32_t best_t = 0xFFFFFFFFu;
+          src_id = 0xFFFFFFFFu;
+          best = -1;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            if (((dirs >> q) & 1u) &&
+                (best < 0 || tk[q] < best_t || (tk[q] == best_t && kk[q] < src_id))) {
               best = q;
-              best_t = tk;
-              src_id = k;
+              best_t = tk[q];
+              src_id = kk[q];
             }
           }
           atomicOr((unsigned long long*)&cwin[best * R + r], 1ull << c);
+        } else {
+          src_id = ids[(r + dir_dr(best)) * 64 + c + dir_dc(best)];
         }
         ids[r * 64 + c] = src_id;
       }
@@ -382,48 +409,54 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
   __syncthreads();
 
   // ---- write the interior back; pheromone applied step by step ------------
-  // Each wave takes blocks of kWriteRows consecutive rows and issues every
-  // LDS read of a block before the arithmetic; the occupancy history of a
-  // lane's cell is gathered into bit vectors (bit u: occupied after step u).
+  // Interior rows are dealt round-robin to the waves, kWriteRows at a time;
+  // every LDS read of a block is issued before its arithmetic, and each
+  // cell's occupancy history is packed into bit vectors (bit u: occupied
+  // after step u).
   constexpr int kWriteRows = 4;
   uint32_t cnt[kTileStatFields] = {0, 0, 0, 0, 0};
-  for (int r0 = h + wave * kWriteRows; r0 < R - h; r0 += nwaves * kWriteRows) {
-    const int c = lane;
-    const int gx = x0 + c;
+  const int c = lane;
+  const int gx = x0 + c;
+  for (int r0 = h + wave; r0 < R - h; r0 += nwaves * kWriteRows) {
     uint64_t ra[kWriteRows], rb[kWriteRows], rw[kWriteRows], rm[kWriteRows];
     uint32_t idv[kWriteRows], hist_a[kWriteRows], hist_b[kWriteRows];
     float va[kWriteRows], vb[kWriteRows];
+    int rr[kWriteRows];
 #pragma unroll
     for (int j = 0; j < kWriteRows; ++j) {
-      const int r = r0 + j < R - h ? r0 + j : R - h - 1;  // rows past the interior repeat the last one, unused
-      ra[j] = H(steps, 0, r);
-      rb[j] = H(steps, 1, r);
-      rw[j] = wall_m[r];
-      rm[j] = moved_m[r];
-      idv[j] = ids[r * 64 + c];
+      const int r = r0 + j * nwaves;
+      rr[j] = r < R - h ? r : R - h - 1;  // rows past the interior repeat the last one, unused
+      ra[j] = H(steps, 0, rr[j]);
+      rb[j] = H(steps, 1, rr[j]);
+      rw[j] = wall_m[rr[j]];
+      rm[j] = moved_m[rr[j]];
+      idv[j] = ids[rr[j] * 64 + c];
       hist_a[j] = 0u;
       hist_b[j] = 0u;
       if (MODE == 1) {
-        va[j] = tau_a[r * 64 + c];
-        vb[j] = tau_b[r * 64 + c];
+        va[j] = tau_a[rr[j] * 64 + c];
+        vb[j] = tau_b[rr[j] * 64 + c];
+      }
+    }
+    if (MODE == 1) {
+      for (int u = 1; u <= steps; ++u) {
 #pragma unroll
-        for (int u = 1; u <= kRowsMaxSteps; ++u) {
-          if (u <= steps) {
-            hist_a[j] |= (uint32_t)((H(u, 0, r) >> c) & 1ull) << u;
-            hist_b[j] |= (uint32_t)((H(u, 1, r) >> c) & 1ull) << u;
-          }
+        for (int j = 0; j < kWriteRows; ++j) {
+          hist_a[j] |= (uint32_t)((H(u, 0, rr[j]) >> c) & 1ull) << u;
+          hist_b[j] |= (uint32_t)((H(u, 1, rr[j]) >> c) & 1ull) << u;
         }
       }
     }
 #pragma unroll
     for (int j = 0; j < kWriteRows; ++j) {
-      const int r = r0 + j;
+      const int r = r0 + j * nwaves;
       if (r >= R - h) break;  // wave-uniform
       const int gy = y0 + r;
       const bool interior = c >= h && c < h + S.IX && gx < S.W && gy < S.H;
-      const uint64_t lb = lane_bit;
       const int g = !interior ? kEmpty
-                              : ((ra[j] & lb) ? kGroupA : ((rb[j] & lb) ? kGroupB : ((rw[j] & lb) ? kWall : kEmpty)));
+                              : ((ra[j] & lane_bit) ? kGroupA
+                                                    : ((rb[j] & lane_bit) ? kGroupB
+                                                                          : ((rw[j] & lane_bit) ? kWall : kEmpty)));
       if (interior) {
         const size_t gi = (size_t)gy * S.W + gx;
         S.code_out[gi] = (uint8_t)g;
