@@ -180,7 +180,7 @@ __device__ void advance_tile(const Scenario& S, uint8_t* smem, int R, int tx, in
   Tile<NW> T = tile_view<NW>(smem, L);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: row loops and addresses stay scalar
   const int nthreads = blockDim.x;
   const int nwaves = blockDim.x >> 6;
   const int nwords = R * NW;

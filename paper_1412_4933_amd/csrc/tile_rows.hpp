@@ -155,7 +155,7 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: row loops and addresses stay scalar
   const int nthreads = blockDim.x;
   const int nwaves = nthreads >> 6;
   const bool mask_wave = wave == 0;
