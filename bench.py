@@ -65,15 +65,17 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, kernel: str):
+def measured_traffic(workload: str, kernel: str, tiling=None):
     """HBM bytes per launch from committed rocprofv3 counter summaries, only
-    if they were taken on the current kernel sources."""
+    if they were taken on the current kernel sources (and the same tiling)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     if rec.get("kernel_src_digest") != kernel_source_digest():
+        return None
+    if tiling is not None and rec.get("tiling") is not None and list(rec["tiling"]) != list(tiling):
         return None
     return rec.get("bytes_per_launch")
 
@@ -284,7 +286,7 @@ def main():
     alg_step = algorithmic_bytes_per_step(mode, cells, agents)
     alg_launch = alg_step * K / dom_n
     achieved = alg_launch / (dom_avg_ms / 1e3) / 1e9
-    traffic = measured_traffic(args.workload, dom)
+    traffic = measured_traffic(args.workload, dom, tiling)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
