@@ -132,7 +132,10 @@ int sim_read_state(sim_handle* h, uint8_t* code, uint32_t* id, float* tau, void*
  * and must be at least 16 x 8.
  *   nw = 1 or 2: multi-wave engine, regions of 64*nw columns (rows <= 1023);
  *   nw = 0:      row-lane engine, regions of 64 columns, rows <= 64,
- *                steps_per_launch <= 8, threads <= 512.
+ *                steps_per_launch <= 8, threads <= 512;
+ *   nw = 3:      the same engine streaming the pheromone from HBM and
+ *                recomputing contest tickets (less LDS per workgroup, so more
+ *                workgroups per compute unit on large grids).
  * SIM_EINVAL if the shape is not allowed or does not fit the LDS.
  * sim_get_tiling writes {nw, rows, steps_per_launch, threads} into out[4].
  */

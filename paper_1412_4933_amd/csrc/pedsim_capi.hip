@@ -118,12 +118,14 @@ namespace {
 
 // Default tiling by grid size (measured on MI355X): the row-lane engine,
 // with more steps per launch on smaller grids (their launches are short, so
-// the fixed cost of a launch weighs more than the wider halo). The first
-// shape that fits the device's LDS is used.
+// the fixed cost of a launch weighs more than the wider halo), and its
+// streaming form on large grids (many tiles per compute unit: the smaller
+// LDS footprint lets four or five workgroups overlap). The first shape that
+// fits the device's LDS is used.
 Tiling default_tiling(bool aco, size_t cells) {
   static const Tiling tiny_opts[] = {{0, 48, 6, 512}, {0, 32, 4, 256}, {1, 32, 1, 256}};
   static const Tiling small_opts[] = {{0, 56, 4, 512}, {0, 48, 3, 512}, {1, 32, 1, 256}};
-  static const Tiling large_opts[] = {{0, 48, 2, 512}, {0, 32, 2, 256}, {1, 32, 1, 256}};
+  static const Tiling large_opts[] = {{3, 48, 2, 256}, {0, 48, 2, 512}, {1, 32, 1, 256}};
   const Tiling* opts = cells < ((size_t)1 << 18) ? tiny_opts : (cells < ((size_t)2 << 20) ? small_opts : large_opts);
   for (int i = 0; i < 3; ++i)
     if (tiling_valid(opts[i], aco, max_dynamic_lds())) return opts[i];

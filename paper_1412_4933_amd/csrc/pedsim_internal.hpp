@@ -17,9 +17,10 @@ constexpr int kModeAco = 1;
 // Tiling of one scenario: regions of `rows` rows advanced `steps` steps per
 // launch (halo 3*steps), `threads` per workgroup. nw = 1 or 2 selects the
 // multi-wave engine on regions of 64*nw columns; nw = 0 selects the row-lane
-// engine on regions of 64 columns and at most 64 rows.
+// engine on regions of 64 columns and at most 64 rows, and nw = 3 its
+// streaming form (pheromone read from HBM, tickets recomputed, less LDS).
 struct Tiling {
-  int nw;       // 0 (row-lane engine), 1 or 2 (multi-wave engine, words per row)
+  int nw;       // 0 / 3 (row-lane engine / streaming), 1 or 2 (multi-wave engine, words per row)
   int rows;     // region rows
   int steps;    // steps per launch (>= 1)
   int threads;  // workgroup size, multiple of 64, <= 1024
@@ -29,8 +30,9 @@ struct Tiling {
 constexpr int kMinInteriorX = 16;
 constexpr int kMinInteriorY = 8;
 
-inline bool rows_engine(const Tiling& tl) { return tl.nw == 0; }
-inline int region_cols(const Tiling& tl) { return tl.nw == 0 ? 64 : 64 * tl.nw; }
+inline bool rows_engine(const Tiling& tl) { return tl.nw == 0 || tl.nw == 3; }
+inline bool rows_stream(const Tiling& tl) { return tl.nw == 3; }
+inline int region_cols(const Tiling& tl) { return rows_engine(tl) ? 64 : 64 * tl.nw; }
 size_t tile_lds_bytes(const Tiling& tl, bool aco);
 bool tiling_valid(const Tiling& tl, bool aco, int max_lds);
 

@@ -91,9 +91,10 @@ __global__ __launch_bounds__(1024) void batch_kernel(BatchPlan P, int j) {
 }
 
 // The same with the row-lane engine (regions of 64 columns).
+template <bool STREAM>
 __global__ __launch_bounds__(kRowsMaxThreads, kRowsMinWavesPerSimd) void batch_rows_kernel(BatchPlan P, int j) {
   extern __shared__ __align__(16) uint8_t smem[];
-  int& s_item = *(int*)(smem + RowsLayout{P.rows, P.k, true}.bytes());
+  int& s_item = *(int*)(smem + RowsLayout{P.rows, P.k, true, STREAM}.bytes());
   const int count = P.counts[j];
   const int total = P.totals[j];
   const BatchEntry* E = P.entries + (size_t)j * P.capacity;
@@ -111,9 +112,9 @@ __global__ __launch_bounds__(kRowsMaxThreads, kRowsMinWavesPerSimd) void batch_r
     const ItemView v = item_view(P, E, lo, item, j);
     const int tx = v.tile % v.S.tiles_x, ty = v.tile / v.S.tiles_x;
     if (v.mode == kModeAco)
-      advance_tile_rows<kModeAco>(v.S, smem, P.rows, P.k, tx, ty, v.tile, v.t0, v.steps, v.last);
+      advance_tile_rows<kModeAco, STREAM>(v.S, smem, P.rows, P.k, tx, ty, v.tile, v.t0, v.steps, v.last);
     else
-      advance_tile_rows<kModeLem>(v.S, smem, P.rows, P.k, tx, ty, v.tile, v.t0, v.steps, v.last);
+      advance_tile_rows<kModeLem, STREAM>(v.S, smem, P.rows, P.k, tx, ty, v.tile, v.t0, v.steps, v.last);
   }
 }
 
@@ -152,7 +153,9 @@ void prepare_batch_kernels() {
                             max_dynamic_lds());
   (void)hipFuncSetAttribute((const void*)batch_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             max_dynamic_lds());
-  (void)hipFuncSetAttribute((const void*)batch_rows_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+  (void)hipFuncSetAttribute((const void*)batch_rows_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            max_dynamic_lds());
+  (void)hipFuncSetAttribute((const void*)batch_rows_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             max_dynamic_lds());
   (void)hipGetLastError();  // an unsupported attribute value must not linger as the last error
   done = true;
@@ -167,8 +170,11 @@ static hipError_t launch_batch_nw(const BatchPlan& P, const Tiling& tl, int j, i
 
 hipError_t launch_batch(const BatchPlan& P, const Tiling& tl, int j, int grid, hipStream_t s) {
   if (rows_engine(tl)) {
-    const size_t lds = RowsLayout{tl.rows, tl.steps, true}.bytes() + kBatchItemBytes;
-    batch_rows_kernel<<<grid, tl.threads, lds, s>>>(P, j);
+    const size_t lds = RowsLayout{tl.rows, tl.steps, true, rows_stream(tl)}.bytes() + kBatchItemBytes;
+    if (rows_stream(tl))
+      batch_rows_kernel<true><<<grid, tl.threads, lds, s>>>(P, j);
+    else
+      batch_rows_kernel<false><<<grid, tl.threads, lds, s>>>(P, j);
     return hipGetLastError();
   }
   return tl.nw == 1 ? launch_batch_nw<1>(P, tl, j, grid, s) : launch_batch_nw<2>(P, tl, j, grid, s);

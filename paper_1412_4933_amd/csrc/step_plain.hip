@@ -21,23 +21,24 @@ __global__ __launch_bounds__(1024) void tile_kernel(Scenario S, int R, uint64_t 
   advance_tile<NW, MODE>(S, smem, R, tile % S.tiles_x, tile / S.tiles_x, tile, t0, steps, last != 0);
 }
 
-template <int MODE>
+template <int MODE, bool STREAM>
 __global__ __launch_bounds__(kRowsMaxThreads, kRowsMinWavesPerSimd) void tile_rows_kernel(Scenario S, int R, int k_max, uint64_t t0,
                                                                     int steps, int last) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int ntiles = S.tiles_x * S.tiles_y;
   const int tile = tile_of_block(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
-  advance_tile_rows<MODE>(S, smem, R, k_max, tile % S.tiles_x, tile / S.tiles_x, tile, t0, steps, last != 0);
+  advance_tile_rows<MODE, STREAM>(S, smem, R, k_max, tile % S.tiles_x, tile / S.tiles_x, tile, t0, steps,
+                                  last != 0);
 }
 
 size_t tile_lds_bytes(const Tiling& tl, bool aco) {
-  if (rows_engine(tl)) return RowsLayout{tl.rows, tl.steps, aco}.bytes();
+  if (rows_engine(tl)) return RowsLayout{tl.rows, tl.steps, aco, rows_stream(tl)}.bytes();
   return tl.nw == 1 ? Layout<1>{tl.rows, aco}.bytes() : Layout<2>{tl.rows, aco}.bytes();
 }
 
 bool tiling_valid(const Tiling& tl, bool aco, int max_lds) {
-  if (tl.nw < 0 || tl.nw > 2) return false;
+  if (tl.nw < 0 || tl.nw > 3) return false;
   if (rows_engine(tl) && (tl.rows > kRowsMaxRows || tl.steps > kRowsMaxSteps || tl.threads > kRowsMaxThreads))
     return false;
   if (tl.steps < 1 || tl.threads < 64 || tl.threads > 1024 || tl.threads % 64) return false;
@@ -74,27 +75,30 @@ static hipError_t launch_one(const Scenario& S, const Tiling& tl, uint64_t t0, i
   return hipGetLastError();
 }
 
-template <int MODE>
+template <int MODE, bool STREAM>
 static hipError_t launch_rows(const Scenario& S, const Tiling& tl, uint64_t t0, int steps, int last, hipStream_t s) {
-  const size_t lds = RowsLayout{tl.rows, tl.steps, MODE == kModeAco}.bytes();
+  const size_t lds = RowsLayout{tl.rows, tl.steps, MODE == kModeAco, STREAM}.bytes();
   static bool attr_done = false;
   if (!attr_done) {
-    (void)hipFuncSetAttribute((const void*)tile_rows_kernel<MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              max_dynamic_lds());
+    (void)hipFuncSetAttribute((const void*)tile_rows_kernel<MODE, STREAM>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, max_dynamic_lds());
     (void)hipGetLastError();  // an unsupported attribute value must not linger as the last error
     attr_done = true;
   }
   const int ntiles = S.tiles_x * S.tiles_y;
   const int blocks = ((ntiles + 7) / 8) * 8;
-  tile_rows_kernel<MODE><<<blocks, tl.threads, lds, s>>>(S, tl.rows, tl.steps, t0, steps, last);
+  tile_rows_kernel<MODE, STREAM><<<blocks, tl.threads, lds, s>>>(S, tl.rows, tl.steps, t0, steps, last);
   return hipGetLastError();
 }
 
 hipError_t launch_tiles(const Scenario& S, const Tiling& tl, int mode, uint64_t t0, int steps, int last,
                         hipStream_t s) {
+  if (rows_stream(tl))
+    return mode == kModeLem ? launch_rows<kModeLem, true>(S, tl, t0, steps, last, s)
+                            : launch_rows<kModeAco, true>(S, tl, t0, steps, last, s);
   if (rows_engine(tl))
-    return mode == kModeLem ? launch_rows<kModeLem>(S, tl, t0, steps, last, s)
-                            : launch_rows<kModeAco>(S, tl, t0, steps, last, s);
+    return mode == kModeLem ? launch_rows<kModeLem, false>(S, tl, t0, steps, last, s)
+                            : launch_rows<kModeAco, false>(S, tl, t0, steps, last, s);
   if (tl.nw == 1)
     return mode == kModeLem ? launch_one<1, kModeLem>(S, tl, t0, steps, last, s)
                             : launch_one<1, kModeAco>(S, tl, t0, steps, last, s);

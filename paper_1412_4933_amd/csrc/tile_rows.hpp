@@ -52,6 +52,7 @@ constexpr int kRowsMinWavesPerSimd = 4;
 struct RowsLayout {
   int R, k;
   bool aco;
+  bool stream;  // pheromone read from HBM, tickets recomputed: no tick or tau arrays
   __host__ __device__ size_t hist() const { return 0; }                                  // [k+1][2][R] u64
   __host__ __device__ size_t wall() const { return hist() + (size_t)(k + 1) * 2 * R * 8; }  // [R] u64
   __host__ __device__ size_t side() const { return wall() + (size_t)R * 8; }             // [6][R] u64
@@ -61,9 +62,9 @@ struct RowsLayout {
   __host__ __device__ size_t ctl() const { return moved() + (size_t)R * 8; }             // 16 u32
   __host__ __device__ size_t ids() const { return ctl() + 64; }                         // [R][64] u32
   __host__ __device__ size_t tick() const { return ids() + (size_t)R * 256; }           // [R][64] u32
-  __host__ __device__ size_t queue() const { return tick() + (size_t)R * 256; }         // [R*64] u16
+  __host__ __device__ size_t queue() const { return tick() + (stream ? 0 : (size_t)R * 256); }  // [R*64] u16
   __host__ __device__ size_t tau() const { return queue() + (size_t)R * 128; }          // [2][R][64] f32
-  __host__ __device__ size_t bytes() const { return tau() + (aco ? (size_t)R * 512 : 0); }
+  __host__ __device__ size_t bytes() const { return tau() + (aco && !stream ? (size_t)R * 512 : 0); }
 };
 
 // Row r-1's value in lane r (0 in lane 0) / row r+1's value in lane r (0 in lane 63).
@@ -134,10 +135,15 @@ __device__ __forceinline__ void stage_issue(const Scenario& S, int R, int x0, in
   }
 }
 
-template <int MODE>
+// STREAM: the pheromone planes are not staged (the draw and the write-back read
+// them from HBM and bring them up to date from the recorded occupancy) and
+// contest tickets are recomputed instead of kept per cell, which leaves ids,
+// masks and the queue as the region's only LDS and lets more workgroups share
+// a compute unit on large grids.
+template <int MODE, bool STREAM = false>
 __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k_max, int tx, int ty, int tile_index,
                                   uint64_t t0, int steps, bool last) {
-  const RowsLayout L{R, k_max, MODE == 1};
+  const RowsLayout L{R, k_max, MODE == 1, STREAM};
   uint64_t* hist = (uint64_t*)(smem + L.hist());
   uint64_t* wall_m = (uint64_t*)(smem + L.wall());
   uint64_t* side = (uint64_t*)(smem + L.side());
@@ -169,7 +175,7 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
   // ---- stage: rows dealt round-robin to the waves, all loads in flight --
   for (int r0 = wave; r0 < R; r0 += nwaves * kStageRows) {
     StageRegs q;
-    stage_issue<MODE>(S, R, x0, y0, r0, nwaves, lane, q);
+    stage_issue<(STREAM ? 0 : MODE)>(S, R, x0, y0, r0, nwaves, lane, q);
 #pragma unroll
     for (int j = 0; j < kStageRows; ++j) {
       const int r = r0 + j * nwaves;
@@ -182,7 +188,7 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
         wall_m[r] = bw;
       }
       ids[r * 64 + lane] = q.id[j];
-      if (MODE == 1) {
+      if (MODE == 1 && !STREAM) {
         tau_a[r * 64 + lane] = q.ta[j];
         tau_b[r * 64 + lane] = q.tb[j];
       }
@@ -237,9 +243,12 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
         twos |= ones & P[q];
         ones |= P[q];
       }
-      const uint64_t pu = from_up(twos), pd = from_down(twos);
-      const uint64_t need = (fA & (twos >> 1)) | (fB & (twos << 1)) | (oA0 & (pu >> 1)) | (oA1 & (pd >> 1)) |
-                            (oB0 & (pu << 1)) | (oB1 & (pd << 1)) | (o2 & pu) | (o3 & pd);
+      uint64_t need = 0ull;  // with recomputed tickets only the choices are queued
+      if (!STREAM) {
+        const uint64_t pu = from_up(twos), pd = from_down(twos);
+        need = (fA & (twos >> 1)) | (fB & (twos << 1)) | (oA0 & (pu >> 1)) | (oA1 & (pd >> 1)) |
+               (oB0 & (pu << 1)) | (oB1 & (pd << 1)) | (o2 & pu) | (o3 & pd);
+      }
       if (row_lane) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) side[q * R + lane] = 0ull;
@@ -277,18 +286,33 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
         const unsigned avail = (bf & (unsigned)(eu >> cfc)) | ((bf & (unsigned)(ed >> cfc)) << 1) |
                                (((unsigned)(eu >> c) & 1u) << 2) | (((unsigned)(ed >> c) & 1u) << 3);
         const Words w = agent_words(id - 1u, t, S.key0, S.key1);
-        tick[r * 64 + c] = w.w0;
+        if (!STREAM) tick[r * 64 + c] = w.w0;
         if (!fwd && (avail & (avail - 1u)) != 0u) {  // two or more side candidates: a choice
           int req;
           if (MODE == 0) {
             req = lem_choose(avail, w.w1, w.w2);
           } else {
             const int gp = is_a ? 0 : 1;
-            const float* tp = is_a ? tau_a : tau_b;
             // candidates 0 FD- (ru, cfc), 1 FD+ (rd, cfc), 2 L- (ru, c), 3 L+ (rd, c):
             // their values at the launch start, advanced to step s with the
             // occupancy of their two rows after each step
-            float tau[4] = {tp[ru * 64 + cfc], tp[rd * 64 + cfc], tp[ru * 64 + c], tp[rd * 64 + c]};
+            float tau[4];
+            if (STREAM) {  // from HBM; a candidate outside the grid is never empty, index 0 stands in
+              const float* tp = S.tau_in + (is_a ? 0 : plane);
+              const int cr[4] = {ru, rd, ru, rd}, cc[4] = {cfc, cfc, c, c};
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                const int gx = x0 + cc[j], gy = y0 + cr[j];
+                const bool in = ((avail >> j) & 1u) && gx >= 0 && gx < S.W && gy >= 0 && gy < S.H;
+                tau[j] = tp[in ? (size_t)gy * S.W + gx : 0];
+              }
+            } else {
+              const float* tp = is_a ? tau_a : tau_b;
+              tau[0] = tp[ru * 64 + cfc];
+              tau[1] = tp[rd * 64 + cfc];
+              tau[2] = tp[ru * 64 + c];
+              tau[3] = tp[rd * 64 + c];
+            }
             for (int u = 1; u <= s; ++u) {
               const uint64_t hu = H(u, gp, ru), hd = H(u, gp, rd);
               const unsigned ob = ((unsigned)(hu >> cfc) & 1u) | (((unsigned)(hd >> cfc) & 1u) << 1) |
@@ -362,8 +386,13 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
             int sr = r + dir_dr(q), sc = c + dir_dc(q);
             sr = sr < 0 ? 0 : (sr >= R ? R - 1 : sr);
             sc = sc < 0 ? 0 : (sc > 63 ? 63 : sc);
-            tk[q] = tick[sr * 64 + sc];
             kk[q] = ids[sr * 64 + sc];
+            if (!STREAM) tk[q] = tick[sr * 64 + sc];
+          }
+          if (STREAM) {  // the contenders' tickets, drawn again (independent chains)
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+              tk[q] = ((dirs >> q) & 1u) ? agent_words(kk[q] - 1u, t, S.key0, S.key1).w0 : 0xFFFFFFFFu;
           }
           uint32_t best_t = 0xFFFFFFFFu;
           src_id = 0xFFFFFFFFu;
@@ -434,8 +463,16 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
       hist_a[j] = 0u;
       hist_b[j] = 0u;
       if (MODE == 1) {
-        va[j] = tau_a[rr[j] * 64 + c];
-        vb[j] = tau_b[rr[j] * 64 + c];
+        if (STREAM) {  // from HBM (interior cells only; index 0 stands in for the rest)
+          const int gy = y0 + rr[j];
+          const bool in = c >= h && c < h + S.IX && gx < S.W && gy < S.H;
+          const size_t gi = in ? (size_t)gy * S.W + gx : 0;
+          va[j] = S.tau_in[gi];
+          vb[j] = S.tau_in[plane + gi];
+        } else {
+          va[j] = tau_a[rr[j] * 64 + c];
+          vb[j] = tau_b[rr[j] * 64 + c];
+        }
       }
     }
     if (MODE == 1) {

@@ -93,7 +93,8 @@ def test_batch_alone_equals_in_the_mix(pedsim):
 
 @pytest.mark.parametrize("tuning", [(1, 32, 1, 256, 1, 1), (1, 48, 2, 512, 2, 0), (2, 40, 2, 1024, 1, 1),
                                     (1, 64, 3, 512, 4, 1), (1, 32, 2, 64, 8, 1),
-                                    (0, 64, 2, 256, 2, 1), (0, 48, 3, 64, 4, 0), (0, 64, 1, 512, 1, 1)])
+                                    (0, 64, 2, 256, 2, 1), (0, 48, 3, 64, 4, 0), (0, 64, 1, 512, 1, 1),
+                                    (3, 48, 2, 256, 4, 1), (3, 32, 3, 128, 6, 0)])
 def test_batch_results_do_not_depend_on_tuning(pedsim, tuning):
     scns = mixed_scenarios(8, seed0=500)
     states = [oracle.State.from_scenario(s) for s in scns]

@@ -42,8 +42,8 @@ def assert_same(sim, st, what=""):
 
 
 # One explicit tiling per engine (nw, rows, steps per launch, threads): the
-# multi-wave engine and the row-lane engine.
-ENGINES = {"multi": (1, 32, 2, 512), "rows": (0, 48, 2, 256)}
+# multi-wave engine, the row-lane engine and its streaming form.
+ENGINES = {"multi": (1, 32, 2, 512), "rows": (0, 48, 2, 256), "stream": (3, 40, 3, 256)}
 
 
 def run_both(pedsim, scn, mode, steps, chunks=(1,), tiling=None):
@@ -269,7 +269,9 @@ TILINGS = [(1, 32, 1, 256), (1, 48, 2, 512), (1, 64, 3, 1024), (2, 64, 2, 1024),
            (1, 96, 2, 128), (1, 32, 1, 64),
            # row-lane engine: regions of 64 columns, at most 64 rows
            (0, 64, 1, 64), (0, 32, 1, 128), (0, 48, 2, 256), (0, 64, 3, 256), (0, 64, 2, 512),
-           (0, 40, 4, 512), (0, 64, 8, 256)]
+           (0, 40, 4, 512), (0, 64, 8, 256),
+           # streaming row-lane engine
+           (3, 48, 2, 256), (3, 64, 3, 64), (3, 32, 1, 512), (3, 56, 4, 128)]
 
 
 @pytest.mark.parametrize("mode", [S.MODE_LEM, S.MODE_ACO])
