@@ -90,7 +90,7 @@ struct sim_batch {
 namespace {
 
 Tiling default_batch_tiling() {
-  static const Tiling opts[] = {{0, 48, 3, 512}, {1, 64, 2, 512}, {1, 32, 1, 256}};
+  static const Tiling opts[] = {{3, 56, 3, 256}, {0, 48, 3, 512}, {1, 32, 1, 256}};
   for (const Tiling& t : opts)
     if (tiling_valid(t, true, max_dynamic_lds() - kBatchItemBytes)) return t;
   return opts[2];
@@ -221,7 +221,7 @@ int sim_batch_create(int32_t capacity, void* d_workspace, size_t workspace_bytes
   b->staging = nullptr;
   b->upload_pending = false;
   b->tl = default_batch_tiling();
-  b->wgs_per_cu = 2;
+  b->wgs_per_cu = 4;  // the default streaming tiling needs ~36 KB of LDS: four workgroups fit a CU
   b->use_graph = 1;
   for (int i = 0; i <= kBatchMaxLaunches; ++i) b->graphs[i] = nullptr;
   b->slots.resize(capacity);
