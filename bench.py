@@ -280,7 +280,7 @@ def main():
     # `stream`: the step kernel's average duration is the region's event time
     # (minus the copy-back launches, if any) over its launch count.
     dom_n = per_kernel["tile_kernel"][1]
-    dom = "tile_rows_kernel" if tiling[0] == 0 else "tile_kernel"  # kernel symbol in traces
+    dom = "tile_rows_kernel" if tiling[0] in (0, 3) else "tile_kernel"  # kernel symbol in traces
     copy_ms = per_kernel["copy_back"][0]
     dom_avg_ms = (ms - copy_ms) / dom_n
     alg_step = algorithmic_bytes_per_step(mode, cells, agents)
