@@ -20,7 +20,7 @@ _LIB = os.path.join(_HERE, "libpedsim_oracle.so")
 # The mutation tests point this at a deliberately broken build of the oracle.
 _LIB_OVERRIDE = os.environ.get("PEDSIM_ORACLE_LIB")
 
-MODE_LEM, MODE_ACO = 0, 1
+MODE_LEM, MODE_ACO, MODE_ACO_TOUR = 0, 1, 2
 
 
 class OracleParams(ctypes.Structure):
@@ -66,6 +66,14 @@ def lib():
                                  ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_void_p]
         L.oracle_run.restype = ctypes.c_int64
+        L.oracle_step_tour.argtypes = [P(OracleParams), ctypes.c_uint64, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.oracle_step_tour.restype = ctypes.c_int64
+        L.oracle_run_tour.argtypes = [P(OracleParams), ctypes.c_uint64, ctypes.c_int64,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p]
+        L.oracle_run_tour.restype = ctypes.c_int64
         L.oracle_counts.argtypes = [P(OracleParams), ctypes.c_void_p, P(ctypes.c_uint64)]
         _lib = L
     return _lib
@@ -99,14 +107,23 @@ def heuristic_weights(beta: int):
 
 
 class State:
-    """Host copy of one scenario's planes, advanced by the oracle."""
+    """Host copy of one scenario's planes, advanced by the oracle.
+
+    `tour` is the tour matrix of the tour variant (one float per agent,
+    index = agent number = id - 1); zeros when not given."""
 
     def __init__(self, code, ids, tau=None, *, seed: int, rho: float = 0.1,
                  dtau: float = 1.0, alpha: int = 1, beta: int = 2, cross_a: int = 1,
-                 cross_b: int = 1, t: int = 0):
+                 cross_b: int = 1, t: int = 0, tour=None):
         self.code = np.ascontiguousarray(code, dtype=np.uint8).copy()
         self.ids = np.ascontiguousarray(ids, dtype=np.uint32).copy()
         self.H, self.W = self.code.shape
+        n = int(self.ids.max()) if self.ids.size else 0
+        if tour is None:
+            self.tour = np.zeros(n, np.float32)
+        else:
+            self.tour = np.ascontiguousarray(tour, dtype=np.float32).copy()
+            assert self.tour.shape == (n,)
         if tau is None:
             self.tau = None
         else:
@@ -119,10 +136,11 @@ class State:
     @classmethod
     def from_scenario(cls, s) -> "State":
         return cls(s.code, s.ids, s.tau, seed=s.seed, rho=s.rho, dtau=s.dtau,
-                   alpha=s.alpha, beta=s.beta, cross_a=s.cross_a, cross_b=s.cross_b)
+                   alpha=s.alpha, beta=s.beta, cross_a=s.cross_a, cross_b=s.cross_b,
+                   tour=getattr(s, "tour", None))
 
     def _tau_ptrs(self, mode):
-        if mode == MODE_ACO:
+        if mode in (MODE_ACO, MODE_ACO_TOUR):
             if self.tau is None:
                 raise ValueError("ACO step needs pheromone planes")
             return self.tau[0].ctypes.data, self.tau[1].ctypes.data
@@ -135,10 +153,16 @@ class State:
         if want_detail:
             req = np.zeros((self.H, self.W), dtype=np.uint8)
             win = np.zeros((self.H, self.W), dtype=np.uint8)
-        moved = lib().oracle_step(ctypes.byref(self.p), mode, self.t, self.code.ctypes.data,
-                                  self.ids.ctypes.data, ta, tb,
-                                  None if req is None else req.ctypes.data,
-                                  None if win is None else win.ctypes.data)
+        rq = None if req is None else req.ctypes.data
+        wn = None if win is None else win.ctypes.data
+        if mode == MODE_ACO_TOUR:
+            moved = lib().oracle_step_tour(ctypes.byref(self.p), self.t, self.code.ctypes.data,
+                                           self.ids.ctypes.data, ta, tb,
+                                           self.tour.ctypes.data if self.tour.size else None,
+                                           rq, wn)
+        else:
+            moved = lib().oracle_step(ctypes.byref(self.p), mode, self.t, self.code.ctypes.data,
+                                      self.ids.ctypes.data, ta, tb, rq, wn)
         if moved < 0:
             raise MemoryError("oracle step failed to allocate")
         self.t += 1
@@ -146,8 +170,13 @@ class State:
 
     def run(self, mode: int, nsteps: int) -> int:
         ta, tb = self._tau_ptrs(mode)
-        moved = lib().oracle_run(ctypes.byref(self.p), mode, self.t, nsteps,
-                                 self.code.ctypes.data, self.ids.ctypes.data, ta, tb)
+        if mode == MODE_ACO_TOUR:
+            moved = lib().oracle_run_tour(ctypes.byref(self.p), self.t, nsteps,
+                                          self.code.ctypes.data, self.ids.ctypes.data, ta, tb,
+                                          self.tour.ctypes.data if self.tour.size else None)
+        else:
+            moved = lib().oracle_run(ctypes.byref(self.p), mode, self.t, nsteps,
+                                     self.code.ctypes.data, self.ids.ctypes.data, ta, tb)
         if moved < 0:
             raise MemoryError("oracle step failed to allocate")
         self.t += nsteps

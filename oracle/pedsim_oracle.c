@@ -16,6 +16,9 @@
  *   3. commit   (Sec. IV.d): winners move, everyone else stays;
  *   4. pheromone (ACO only; eq. 3 then eq. 4, Sec. IV.d): every cell of both
  *      planes evaporates, then gains the deposit if its group stands on it.
+ * A second ACO variant (mode 2) keeps the paper's tour matrix (Sec. IV.a):
+ * every move adds its length to the agent's tour length L_k, and the deposit
+ * of eq. 4 becomes eq. 5's amount, dtau / L_k, on the cell the agent entered.
  *
  * Readings taken where the paper is silent (each listed in the design notes):
  *   - frame: x = column, y = row; group A (code 1) heads +x, group B (code 2)
@@ -49,6 +52,12 @@
  *     (r0, k) among the requesters.
  *   - deposit (eq. 4 with a constant amount): dtau on every cell occupied by
  *     the group after the commit; keep = fl(1 - rho).
+ *   - tour variant (eq. 5, Sec. IV.a and IV.d): the tour matrix holds one
+ *     float per agent (index k); a move adds the distance between the two
+ *     cell centres, 1 for F and L-/L+ and fl(sqrt 2) for FD-/FD+, by one
+ *     float addition; the cell the agent enters gains fl(dtau / L_k) with the
+ *     increased L_k (dtau = 1 gives eq. 5's 1/L_k), after its evaporation;
+ *     agents that stay deposit nothing.
  * All float arithmetic is IEEE binary32, one operation at a time, without
  * contraction into fused multiply-adds (built with -ffp-contract=off) and
  * with subnormals kept.
@@ -268,29 +277,33 @@ static int request_of(const oracle_params *p, int mode, uint64_t t, const uint8_
 }
 
 /*
- * One step in place. mode 0 = LEM, 1 = ACO (tau planes required).
+ * One step in place. mode 0 = LEM, 1 = ACO, 2 = ACO with the tour matrix
+ * (tau planes required for 1 and 2, tour[N] for 2).
  * req_out (optional, H*W bytes): each agent's request code, 0 elsewhere.
  * win_out (optional, H*W bytes): for each cell empty at t that received an
  *   agent, 1 + (dy+1)*3 + (dx+1) where (dx, dy) points from the cell to the
  *   winner's old cell; 0 elsewhere.
  * Returns the number of agents that moved, or -1 on allocation failure.
  */
-int64_t oracle_step(const oracle_params *p, int32_t mode, uint64_t t, uint8_t *code,
-                    uint32_t *id, float *tau_a, float *tau_b, uint8_t *req_out,
-                    uint8_t *win_out) {
+static int64_t step_any(const oracle_params *p, int32_t mode, uint64_t t, uint8_t *code,
+                        uint32_t *id, float *tau_a, float *tau_b, float *tour,
+                        uint8_t *req_out, uint8_t *win_out) {
   const int W = p->W, H = p->H;
   const size_t cells = (size_t)W * (size_t)H;
   uint8_t *req = (uint8_t *)calloc(cells, 1);
   uint8_t *new_code = (uint8_t *)malloc(cells);
   uint32_t *new_id = (uint32_t *)malloc(cells * sizeof(uint32_t));
+  uint8_t *entered = (uint8_t *)calloc(cells, 1); /* mode 2: group that entered the cell */
   float eta_diag = heuristic_weight(D2_DIAGONAL, p->beta);
   float eta_lat = heuristic_weight(D2_LATERAL, p->beta);
+  const float diagonal_step = (float)sqrt(2.0);
   int64_t moved = 0;
   int x, y;
-  if (!req || !new_code || !new_id) {
+  if (!req || !new_code || !new_id || !entered) {
     free(req);
     free(new_code);
     free(new_id);
+    free(entered);
     return -1;
   }
   if (win_out) memset(win_out, 0, cells);
@@ -343,6 +356,12 @@ int64_t oracle_step(const oracle_params *p, int32_t mode, uint64_t t, uint8_t *c
         new_code[n] = O_EMPTY;
         new_id[n] = 0;
         moved += 1;
+        if (mode == 2) {
+          /* the tour grows by the length of this move */
+          const float len = (best_dx != 0 && best_dy != 0) ? diagonal_step : 1.0f;
+          tour[best_k] = tour[best_k] + len;
+          entered[c] = code[n];
+        }
         if (win_out) win_out[c] = (uint8_t)(1 + (best_dy + 1) * 3 + (best_dx + 1));
       }
     }
@@ -364,10 +383,40 @@ int64_t oracle_step(const oracle_params *p, int32_t mode, uint64_t t, uint8_t *c
       tau_b[c] = vb;
     }
   }
+
+  /* 4'. tour variant: evaporation (eq. 3), then eq. 5's deposit on entered cells */
+  if (mode == 2) {
+    float rho = p->rho;
+    float keep = 1.0f - rho;
+    size_t c;
+    for (c = 0; c < cells; ++c) {
+      float evaporated_a = keep * tau_a[c];
+      float evaporated_b = keep * tau_b[c];
+      if (entered[c] == O_A) evaporated_a = evaporated_a + p->dtau / tour[id[c] - 1u];
+      if (entered[c] == O_B) evaporated_b = evaporated_b + p->dtau / tour[id[c] - 1u];
+      tau_a[c] = evaporated_a;
+      tau_b[c] = evaporated_b;
+    }
+  }
   free(req);
   free(new_code);
   free(new_id);
+  free(entered);
   return moved;
+}
+
+int64_t oracle_step(const oracle_params *p, int32_t mode, uint64_t t, uint8_t *code,
+                    uint32_t *id, float *tau_a, float *tau_b, uint8_t *req_out,
+                    uint8_t *win_out) {
+  if (mode != 0 && mode != 1) return -1;
+  return step_any(p, mode, t, code, id, tau_a, tau_b, NULL, req_out, win_out);
+}
+
+/* One step of the tour variant (mode 2); tour[k] is agent k's tour length. */
+int64_t oracle_step_tour(const oracle_params *p, uint64_t t, uint8_t *code, uint32_t *id,
+                         float *tau_a, float *tau_b, float *tour, uint8_t *req_out,
+                         uint8_t *win_out) {
+  return step_any(p, 2, t, code, id, tau_a, tau_b, tour, req_out, win_out);
 }
 
 /* Crossing and population counts of the current state:
@@ -395,6 +444,16 @@ int64_t oracle_run(const oracle_params *p, int32_t mode, uint64_t t0, int64_t ns
   int64_t s, moved = 0;
   for (s = 0; s < nsteps; ++s) {
     moved = oracle_step(p, mode, t0 + (uint64_t)s, code, id, tau_a, tau_b, NULL, NULL);
+    if (moved < 0) return -1;
+  }
+  return moved;
+}
+
+int64_t oracle_run_tour(const oracle_params *p, uint64_t t0, int64_t nsteps, uint8_t *code,
+                        uint32_t *id, float *tau_a, float *tau_b, float *tour) {
+  int64_t s, moved = 0;
+  for (s = 0; s < nsteps; ++s) {
+    moved = oracle_step_tour(p, t0 + (uint64_t)s, code, id, tau_a, tau_b, tour, NULL, NULL);
     if (moved < 0) return -1;
   }
   return moved;

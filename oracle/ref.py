@@ -6,7 +6,8 @@ Philox, numpy float32 scalars for every float operation) so that an indexing
 or ordering slip in either one shows up as a disagreement. Same readings of
 the paper as the C oracle (request per Sec. III / IV.b-c with eq. 1 or eq. 2,
 scatter-to-gather resolve per Sec. IV.d, evaporation eq. 3 then deposit
-eq. 4).
+eq. 4; mode 2 keeps a tour length per agent and deposits eq. 5's amount on
+the cell an agent enters).
 """
 from __future__ import annotations
 
@@ -47,12 +48,14 @@ def _weight(d2, beta):
     return F32(float(d2) ** (-0.5 * beta))
 
 
-def step(code, ids, tau, *, mode, t, seed, rho, dtau, alpha, beta):
-    """One step on copies; returns (code, ids, tau, req, moved)."""
+def step(code, ids, tau, *, mode, t, seed, rho, dtau, alpha, beta, tour=None):
+    """One step on copies; returns (code, ids, tau, req, moved), or with
+    mode 2 (code, ids, tau, tour, req, moved)."""
     H, W = code.shape
     code = code.copy()
     ids = ids.copy()
     tau = None if tau is None else tau.copy()
+    tour = None if tour is None else tour.copy()
     key = (seed & MASK, seed >> 32)
 
     def words(k):
@@ -138,11 +141,29 @@ def step(code, ids, tau, *, mode, t, seed, rho, dtau, alpha, beta):
                 best[(tx, ty)] = cand
     new_code = code.copy()
     new_ids = ids.copy()
-    for (tx, ty), (_, _, sx, sy) in best.items():
+    arrivals = {}
+    for (tx, ty), (_, k, sx, sy) in best.items():
         new_code[ty, tx] = code[sy, sx]
         new_ids[ty, tx] = ids[sy, sx]
         new_code[sy, sx] = 0
         new_ids[sy, sx] = 0
+        if mode == 2:
+            # length of the move between cell centres: 1 straight, sqrt 2 diagonal
+            length = F32(math.sqrt(2.0)) if (tx != sx and ty != sy) else F32(1.0)
+            tour[k] = F32(tour[k] + length)
+            arrivals[(tx, ty)] = (int(code[sy, sx]), k)
+    if mode == 2:
+        keep = F32(F32(1.0) - F32(rho))
+        for g in (1, 2):
+            plane = tau[g - 1]
+            for y in range(H):
+                for x in range(W):
+                    v = F32(keep * plane[y, x])
+                    a = arrivals.get((x, y))
+                    if a is not None and a[0] == g:
+                        v = F32(v + F32(F32(dtau) / tour[a[1]]))
+                    plane[y, x] = v
+        return new_code, new_ids, tau, tour, req, len(best)
     if mode == 1:
         keep = F32(F32(1.0) - F32(rho))
         for g in (1, 2):

@@ -30,7 +30,7 @@ from typing import List, Optional
 import numpy as np
 
 EMPTY, GROUP_A, GROUP_B, WALL = 0, 1, 2, 3
-MODE_LEM, MODE_ACO = 0, 1
+MODE_LEM, MODE_ACO, MODE_ACO_TOUR = 0, 1, 2
 
 
 @dataclasses.dataclass
@@ -54,6 +54,7 @@ class Scenario:
     dtau: float = 1.0
     alpha: int = 1
     beta: int = 2
+    tour: Optional[np.ndarray] = None  # float32 [N] initial tour lengths (tour variant), None = zeros
 
     @property
     def cross_a(self) -> int:
@@ -75,6 +76,7 @@ class Scenario:
             code=self.code.copy(),
             ids=self.ids.copy(),
             tau=None if self.tau is None else self.tau.copy(),
+            tour=None if self.tour is None else self.tour.copy(),
         )
 
 
@@ -153,7 +155,7 @@ def make_scenario(W: int, H: int, n_a: int, n_b: int, *, band_a: int,
         add_obstacles(code, rng, obstacle_frac)
     ids, b_a, b_b = place_groups(code, n_a, n_b, band_a, band_b, rng)
     if with_tau is None:
-        with_tau = mode == MODE_ACO
+        with_tau = mode in (MODE_ACO, MODE_ACO_TOUR)
     tau = np.full((2, H, W), np.float32(tau0), dtype=np.float32) if with_tau else None
     return Scenario(W=W, H=H, code=code, ids=ids, tau=tau, seed=seed, band_a=b_a,
                     band_b=b_b, n_a=n_a, n_b=n_b, mode=mode, steps=steps, tau0=tau0,
@@ -188,6 +190,12 @@ def aco_1024x512(seed: int = 1) -> Scenario:
     """ACO, 1024x512, 50,000 agents per group in 64-column bands (widened to
     99), tau0=1, rho=0.1, dtau=1, alpha=1, beta=2, 2,000 steps."""
     return make_scenario(1024, 512, 50000, 50000, band_a=64, seed=seed, mode=MODE_ACO,
+                         steps=2000)
+
+
+def aco_tour_1024x512(seed: int = 1) -> Scenario:
+    """The 1024x512 ACO workload run with the tour variant (eq. 5 deposits)."""
+    return make_scenario(1024, 512, 50000, 50000, band_a=64, seed=seed, mode=MODE_ACO_TOUR,
                          steps=2000)
 
 

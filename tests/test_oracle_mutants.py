@@ -34,6 +34,18 @@ MUTANTS = {
     "b_heads_plus_x": ("return group == O_A ? 1 : -1;", "return 1;"),
     "forward_first_dropped": ("if (free_cell(p, code, x + d, y)) return O_REQ_F;", ""),
     "other_groups_pheromone": ("(g == O_A) ? tau_a : tau_b", "(g == O_A) ? tau_b : tau_a"),
+    "tour_diagonal_counts_one": ("(best_dx != 0 && best_dy != 0) ? diagonal_step : 1.0f", "1.0f"),
+    "tour_deposit_on_occupied": ("if (entered[c] == O_A) evaporated_a",
+                                 "if (code[c] == O_A) evaporated_a"),
+    "tour_deposit_not_divided": ("evaporated_a + p->dtau / tour[id[c] - 1u]",
+                                 "evaporated_a + p->dtau"),
+    "tour_entered_cell_not_evaporated": (
+        "float evaporated_a = keep * tau_a[c];",
+        "float evaporated_a = entered[c] == O_A ? tau_a[c] : keep * tau_a[c];"),
+    "tour_b_deposit_on_a_plane": (
+        "if (entered[c] == O_B) evaporated_b = evaporated_b + p->dtau / tour[id[c] - 1u];",
+        "if (entered[c] == O_B) evaporated_a = evaporated_a + p->dtau / tour[id[c] - 1u];"),
+    "tour_group_of_target_not_mover": ("entered[c] = code[n];", "entered[c] = code[c];"),
 }
 
 

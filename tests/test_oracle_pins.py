@@ -313,7 +313,7 @@ def check_step_invariants(code0, ids0, code1, ids1, req, moved, tau1=None):
         assert np.all(np.isfinite(tau1)) and np.all(tau1 >= 0)
 
 
-@pytest.mark.parametrize("mode", [oracle.MODE_LEM, oracle.MODE_ACO])
+@pytest.mark.parametrize("mode", [oracle.MODE_LEM, oracle.MODE_ACO, oracle.MODE_ACO_TOUR])
 @pytest.mark.parametrize("seed,obst", [(3, 0.0), (4, 0.08)])
 def test_invariants_every_step(mode, seed, obst):
     s = S.make_scenario(64, 32, 260, 240, band_a=6, seed=seed, mode=mode,
@@ -324,7 +324,7 @@ def test_invariants_every_step(mode, seed, obst):
         c0, i0 = st.code.copy(), st.ids.copy()
         moved, req, win = st.step(mode, want_detail=True)
         check_step_invariants(c0, i0, st.code, st.ids, req, moved,
-                              st.tau if mode == oracle.MODE_ACO else None)
+                              st.tau if mode != oracle.MODE_LEM else None)
         now = st.counts()
         assert now[0] == last[0] and now[1] == last[1]
         assert now[2] >= last[2] and now[3] >= last[3]  # crossings are monotone
@@ -531,3 +531,133 @@ def test_python_reference_agrees_bit_for_bit(mode, alpha, beta, seed):
         assert moved == m2
         assert np.array_equal(code, st.code) and np.array_equal(ids, st.ids)
         assert np.array_equal(tau.view(np.uint32), st.tau.view(np.uint32))
+
+
+# ----------------------------------------------------------------------------
+# Tour variant: tour matrix (Sec. IV.a) and eq. 5's deposit dtau / L_k
+# ----------------------------------------------------------------------------
+
+def _keep_error():
+    keep = Fraction(float(np.float32(1.0) - np.float32(0.1)))
+    return float(abs(keep / Fraction(9, 10) - 1))
+
+
+def test_tour_lone_agent_walk_closed_form():
+    """A lone A agent on an empty corridor walks one cell per step: after t
+    moves its tour length is exactly t. The cell it enters at move j holds,
+    n steps after the start, tau0 0.9^n + 0.9^(n-j) / j in real arithmetic
+    (evaporation first, then eq. 5's deposit, nothing while it stands still);
+    every other cell and the whole B plane hold tau0 0.9^n."""
+    W, H, y0 = 12, 3, 1  # a one-row corridor: at the far end it has nowhere to go
+    code = S.wall_frame(W, H)
+    code[y0, 0] = S.GROUP_A
+    st = oracle.State.from_scenario(S.from_grid(code, tau=np.ones((2, H, W), np.float32)))
+    n = W - 1 + 4  # four more steps standing in the last column
+    for t in range(1, n + 1):
+        st.step(oracle.MODE_ACO_TOUR)
+        assert st.tour[0] == np.float32(min(t, W - 1))
+    bound = (n + 3) * (_keep_error() + 2.0 ** -24) * 1.01
+    for y in range(H):
+        for x in range(W):
+            exact_b = 0.9 ** n
+            assert abs(float(st.tau[1, y, x]) / exact_b - 1) <= bound
+            exact_a = 0.9 ** n
+            if y == y0 and x >= 1:
+                exact_a += 0.9 ** (n - x) / x
+            assert abs(float(st.tau[0, y, x]) / exact_a - 1) <= bound, (x, y)
+
+
+@pytest.mark.parametrize("group", [S.GROUP_A, S.GROUP_B])
+def test_tour_diagonal_move_adds_sqrt2(group):
+    """Walls leave one empty candidate, the forward diagonal on the +y side:
+    the agent takes it (both rules take a lone candidate), its tour becomes
+    the float nearest sqrt 2, and the entered cell gains 1/sqrt 2 on its own
+    group's plane; the next, straight move adds exactly 1."""
+    W, H, y0 = 6, 5, 2
+    code = S.wall_frame(W, H)
+    d = 1 if group == S.GROUP_A else -1
+    x0 = 0 if group == S.GROUP_A else W - 1
+    code[y0, x0] = group
+    for (x, y) in ((x0 + d, y0), (x0 + d, y0 - 1), (x0, y0 - 1), (x0, y0 + 1)):
+        code[y, x] = S.WALL
+    st = oracle.State.from_scenario(S.from_grid(code, tau=np.ones((2, H, W), np.float32)))
+    st.step(oracle.MODE_ACO_TOUR)
+    assert st.code[y0 + 1, x0 + d] == group
+    sqrt2 = math.sqrt(2.0)
+    assert abs(float(st.tour[0]) - sqrt2) <= 2.0 ** -24 * sqrt2
+    g, o = group - 1, 2 - group
+    e = _keep_error() + 2.0 ** -24
+    want = 0.9 + 1 / sqrt2
+    assert abs(float(st.tau[g, y0 + 1, x0 + d]) / want - 1) <= 4 * e
+    assert abs(float(st.tau[o, y0 + 1, x0 + d]) / 0.9 - 1) <= 2 * e
+    st.step(oracle.MODE_ACO_TOUR)
+    assert st.code[y0 + 1, x0 + 2 * d] == group
+    assert abs(float(st.tour[0]) - (sqrt2 + 1)) <= 2.0 ** -23 * (sqrt2 + 1)
+    want = 0.81 + 1 / (sqrt2 + 1)
+    assert abs(float(st.tau[g, y0 + 1, x0 + 2 * d]) / want - 1) <= 6 * e
+
+
+def _positions_xy(ids):
+    ys, xs = np.nonzero(ids)
+    return {int(ids[y, x]) - 1: (int(x), int(y)) for y, x in zip(ys, xs)}
+
+
+@pytest.mark.parametrize("seed,obst,initial", [(6, 0.0, False), (7, 0.07, True)])
+def test_tour_lengths_and_deposits_follow_displacements(seed, obst, initial):
+    """On a crowd, every agent's tour length equals its initial value plus 1
+    per straight and sqrt 2 per diagonal move, the moves read off the
+    successive positions (float accumulation error only); and every step,
+    tau_g(t+1) - keep tau_g(t) is dtau / L_k on a cell that an agent of g
+    has just entered (L_k after that move) and 0 elsewhere, up to rounding."""
+    s = S.make_scenario(64, 32, 260, 240, band_a=6, seed=seed, mode=S.MODE_ACO_TOUR,
+                        obstacle_frac=obst, with_tau=True, dtau=0.75)
+    n = s.agents
+    tour0 = (np.random.default_rng(seed).random(n) * 40).astype(np.float32) if initial \
+        else np.zeros(n, np.float32)
+    s.tour = tour0
+    st = oracle.State.from_scenario(s)
+    keep = float(np.float32(1.0) - np.float32(0.1))
+    length = tour0.astype(np.float64)
+    moves = np.zeros(n, np.int64)
+    pos = _positions_xy(st.ids)
+    for _ in range(60):
+        code0, tau0 = st.code.copy(), st.tau.astype(np.float64)
+        st.step(oracle.MODE_ACO_TOUR)
+        new = _positions_xy(st.ids)
+        expect = np.zeros((2, st.H, st.W))
+        for k, (x, y) in new.items():
+            x0, y0 = pos[k]
+            if (x, y) != (x0, y0):
+                length[k] += math.sqrt(2.0) if (x != x0 and y != y0) else 1.0
+                moves[k] += 1
+                expect[int(st.code[y, x]) - 1, y, x] = 0.75 / length[k]
+        pos = new
+        grow = st.tau.astype(np.float64) - keep * tau0
+        rel = (moves.max() + 2) * 2.0 ** -23
+        tol = 3 * 2.0 ** -24 * (keep * tau0 + expect) + expect * rel
+        assert np.all(np.abs(grow - expect) <= tol)
+        assert np.array_equal(code0 == S.WALL, st.code == S.WALL)
+    assert moves.sum() > 0
+    err = np.abs(st.tour.astype(np.float64) - length)
+    assert np.all(err <= (moves + 2) * 2.0 ** -23 * np.maximum(length, 1.0))
+
+
+@pytest.mark.parametrize("alpha,beta,seed,initial", [(1, 2, 8, False), (2, 1, 9, True)])
+def test_tour_python_reference_agrees_bit_for_bit(alpha, beta, seed, initial):
+    s = S.make_scenario(26, 12, 45, 40, band_a=4, seed=seed, mode=S.MODE_ACO_TOUR,
+                        obstacle_frac=0.06, with_tau=True, alpha=alpha, beta=beta,
+                        rho=0.05, dtau=0.5)
+    if initial:
+        s.tour = (np.random.default_rng(seed).random(s.agents) * 9).astype(np.float32)
+    st = oracle.State.from_scenario(s)
+    code, ids, tau = s.code.copy(), s.ids.copy(), s.tau.copy()
+    tour = st.tour.copy()
+    for t in range(30):
+        moved = st.step(oracle.MODE_ACO_TOUR)
+        code, ids, tau, tour, req, m2 = ref.step(code, ids, tau, mode=2, t=t, seed=seed,
+                                                 rho=0.05, dtau=0.5, alpha=alpha, beta=beta,
+                                                 tour=tour)
+        assert moved == m2
+        assert np.array_equal(code, st.code) and np.array_equal(ids, st.ids)
+        assert np.array_equal(tau.view(np.uint32), st.tau.view(np.uint32))
+        assert np.array_equal(tour.view(np.uint32), st.tour.view(np.uint32))
