@@ -13,6 +13,9 @@
  *   commit    winners move, everybody else stays;
  *   pheromone (ACO) both planes evaporate (eq. 3) and gain a deposit on the
  *             cells their group occupies (eq. 4).
+ * A second ACO variant keeps the tour matrix of Sec. IV.a (one tour length
+ * per agent, grown by every move) and deposits eq. 5's amount dtau / L_k on
+ * the cell an agent enters (sim_attach_tour, sim_step_aco_tour).
  *
  * Frame and encoding
  *   Cell (x, y), x = column 0..W-1, y = row 0..H-1, flat index y*W + x
@@ -63,9 +66,11 @@ extern "C" {
 #define SIM_EHIP (-4)     /* a HIP runtime call failed */
 #define SIM_ENOTAU (-5)   /* ACO step on a handle created without pheromone */
 #define SIM_EFULL (-6)    /* batch has no free slot */
+#define SIM_ENOTOUR (-7)  /* tour step on a handle without a tour array */
 
 #define SIM_MODE_LEM 0
 #define SIM_MODE_ACO 1
+#define SIM_MODE_ACO_TOUR 2
 
 typedef struct sim_handle sim_handle;
 
@@ -115,6 +120,30 @@ int sim_step_lem(sim_handle* h, int32_t nsteps, void* stream);
  * asynchronously; SIM_ENOTAU if the handle has no pheromone planes. */
 int sim_step_aco(sim_handle* h, int32_t nsteps, void* stream);
 
+/*
+ * Tour variant (eq. 5 with the tour matrix of Sec. IV.a and IV.d). Attach the
+ * caller-owned tour array d_tour: float [N], entry k = the tour length of
+ * agent k (id k + 1), finite and >= 0 (0 for a fresh start), plus a second
+ * caller-owned float [N] buffer d_tour_shadow that the library uses as the
+ * other half of its ping-pong. N is the number of agents of the state given
+ * to sim_create; with N = 0 both may be NULL. The values are validated on the
+ * device (SIM_ESTATE if one is negative or not finite); synchronises
+ * `stream`. Attaching again replaces the arrays.
+ */
+int sim_attach_tour(sim_handle* h, float* d_tour, float* d_tour_shadow, void* stream);
+
+/*
+ * Run nsteps (>= 0) steps of the tour variant, asynchronously: requests,
+ * resolution and evaporation as in sim_step_aco; a winner's tour length
+ * grows by the length of its move (1 for F and L-/L+, fl(sqrt 2) for FD-/FD+,
+ * one float addition), and only the cell it enters gains fl(dtau / L_k) with
+ * the grown L_k, on its group's plane, after that cell's evaporation
+ * (dtau = 1 gives eq. 5's 1/L_k). Once the stream has reached the end of the
+ * call, d_tour holds the tour lengths after the last step. SIM_ENOTAU
+ * without pheromone planes, SIM_ENOTOUR without an attached tour array.
+ */
+int sim_step_aco_tour(sim_handle* h, int32_t nsteps, void* stream);
+
 /* Counters after the last completed step; synchronises `stream`. */
 int sim_stats(sim_handle* h, sim_stats_t* out, void* stream);
 
@@ -125,7 +154,8 @@ int sim_stats(sim_handle* h, sim_stats_t* out, void* stream);
 int sim_read_state(sim_handle* h, uint8_t* code, uint32_t* id, float* tau, void* stream);
 
 /*
- * Tiling of the step kernel for `mode` (results never depend on it): each
+ * Tiling of the step kernel for `mode` (SIM_MODE_*; results never depend on
+ * it; the tour variant accepts nw = 0 only): each
  * workgroup of `threads` lanes (multiple of 64, <= 1024) stages a region of
  * `rows` rows in LDS and advances it `steps_per_launch` steps per launch; the
  * tile interior is the region minus 3*steps_per_launch cells on every side
@@ -144,7 +174,7 @@ int sim_set_tiling(sim_handle* h, int32_t mode, int32_t nw, int32_t rows, int32_
 int sim_get_tiling(sim_handle* h, int32_t mode, int32_t out[4]);
 
 /*
- * Instrumentation: run nsteps steps of `mode` (SIM_MODE_LEM or SIM_MODE_ACO)
+ * Instrumentation: run nsteps steps of `mode` (a SIM_MODE_* value)
  * exactly as sim_step_* does, but bracket every kernel launch with HIP events
  * recorded on `stream`, and add each kernel kind's elapsed milliseconds into
  * kernel_ms[kind] and its launch count into launches[kind] (arrays of

@@ -92,7 +92,7 @@ namespace {
 Tiling default_batch_tiling() {
   static const Tiling opts[] = {{3, 56, 3, 256}, {0, 48, 3, 512}, {1, 32, 1, 256}};
   for (const Tiling& t : opts)
-    if (tiling_valid(t, true, max_dynamic_lds() - kBatchItemBytes)) return t;
+    if (tiling_valid(t, kModeAco, max_dynamic_lds() - kBatchItemBytes)) return t;
   return opts[2];
 }
 
@@ -345,7 +345,7 @@ int sim_batch_set_tuning(sim_batch* b, int32_t nw, int32_t rows, int32_t steps_p
                          int32_t wgs_per_cu, int32_t use_graph) {
   if (!b || wgs_per_cu < 1 || wgs_per_cu > 32) return SIM_EINVAL;
   const Tiling tl{nw, rows, steps_per_launch, threads};
-  if (!tiling_valid(tl, true, max_dynamic_lds() - kBatchItemBytes)) return SIM_EINVAL;
+  if (!tiling_valid(tl, kModeAco, max_dynamic_lds() - kBatchItemBytes)) return SIM_EINVAL;
   for (int i = 0; i < b->capacity; ++i) {
     if (!b->slots[i].used) continue;
     HostSlot probe = b->slots[i];

@@ -72,6 +72,7 @@ Scenario base_scenario(const sim_params* p) {
   S.dtau = p->dtau;
   S.eta_diag = heuristic(2.0, p->beta);
   S.eta_lat = heuristic(5.0, p->beta);
+  S.step_diag = sqrtf(2.0f);
   S.alpha = p->alpha;
   S.cross_a = p->cross_a;
   S.cross_b = p->cross_b;
@@ -89,7 +90,7 @@ void set_geometry(Scenario& S, const Tiling& tl) {
 // Validate caller planes on the device (codes, id/code consistency, ids
 // exactly 1..N, pheromone finite and >= 0); synchronises the stream.
 int validate_state(const sim_params* p, const uint8_t* d_code, const uint32_t* d_id, const float* d_tau,
-                   uint8_t* scratch, const ScratchLayout& L, hipStream_t s) {
+                   uint8_t* scratch, const ScratchLayout& L, hipStream_t s, uint64_t* agents) {
   const size_t cells = (size_t)p->W * (size_t)p->H;
   unsigned long long* counters = (unsigned long long*)(scratch + L.totals) + kTileStatFields;
   unsigned long long host_counters[3];
@@ -99,6 +100,7 @@ int validate_state(const sim_params* p, const uint8_t* d_code, const uint32_t* d
   PEDSIM_HIP(hipStreamSynchronize(s));
   if (host_counters[2]) return SIM_ESTATE;
   const unsigned long long n = host_counters[0] + host_counters[1];
+  if (agents) *agents = n;
   if (n > 0) {
     uint32_t* bitmap = (uint32_t*)(scratch + L.id2);
     PEDSIM_HIP(hipMemsetAsync(bitmap, 0, (n + 31) / 32 * sizeof(uint32_t), s));
@@ -122,13 +124,22 @@ namespace {
 // streaming form on large grids (many tiles per compute unit: the smaller
 // LDS footprint lets four or five workgroups overlap). The first shape that
 // fits the device's LDS is used.
-Tiling default_tiling(bool aco, size_t cells) {
+// The tour variant runs on the row-lane engine with the pheromone in LDS
+// (its deposits depend on per-move tour lengths, so they are applied in LDS
+// as they happen).
+Tiling default_tiling(int mode, size_t cells) {
   static const Tiling tiny_opts[] = {{0, 48, 6, 512}, {0, 32, 4, 256}, {1, 32, 1, 256}};
   static const Tiling small_opts[] = {{0, 56, 4, 512}, {0, 48, 3, 512}, {1, 32, 1, 256}};
   static const Tiling large_opts[] = {{3, 48, 2, 256}, {0, 48, 2, 512}, {1, 32, 1, 256}};
-  const Tiling* opts = cells < ((size_t)1 << 18) ? tiny_opts : (cells < ((size_t)2 << 20) ? small_opts : large_opts);
+  static const Tiling tour_tiny[] = {{0, 48, 6, 512}, {0, 32, 4, 256}, {0, 32, 1, 256}};
+  static const Tiling tour_small[] = {{0, 56, 4, 512}, {0, 48, 3, 512}, {0, 32, 1, 256}};
+  static const Tiling tour_large[] = {{0, 48, 2, 512}, {0, 40, 2, 256}, {0, 32, 1, 256}};
+  const int size = cells < ((size_t)1 << 18) ? 0 : (cells < ((size_t)2 << 20) ? 1 : 2);
+  const Tiling* const plain[3] = {tiny_opts, small_opts, large_opts};
+  const Tiling* const tour[3] = {tour_tiny, tour_small, tour_large};
+  const Tiling* opts = mode == kModeAcoTour ? tour[size] : plain[size];
   for (int i = 0; i < 3; ++i)
-    if (tiling_valid(opts[i], aco, max_dynamic_lds())) return opts[i];
+    if (tiling_valid(opts[i], mode, max_dynamic_lds())) return opts[i];
   return opts[2];
 }
 
@@ -143,16 +154,18 @@ struct sim_handle {
   int stats_entries;
   unsigned long long* totals;
   Scenario base;   // parameters shared by every launch
-  Tiling tiling[2];
+  Tiling tiling[3];
   uint64_t t;      // index of the next step
+  uint64_t agents; // number of agents (ids 1..agents)
 };
 
 namespace {
 
-hipError_t copy_planes(const Planes& dst, const Planes& src, size_t cells, bool tau, hipStream_t s) {
+hipError_t copy_planes(const Planes& dst, const Planes& src, size_t cells, bool tau, size_t tour, hipStream_t s) {
   hipError_t e = hipMemcpyAsync(dst.code, src.code, cells, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(dst.id, src.id, cells * 4, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess && tau) e = hipMemcpyAsync(dst.tau, src.tau, cells * 8, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && tour) e = hipMemcpyAsync(dst.tour, src.tour, tour * 4, hipMemcpyDeviceToDevice, s);
   return e;
 }
 
@@ -187,7 +200,8 @@ int run_steps(sim_handle* h, int mode, int32_t nsteps, hipStream_t s, hipEvent_t
   Scenario S = h->base;
   set_geometry(S, tl);
   const size_t cells = (size_t)S.W * (size_t)S.H;
-  const bool aco = mode == kModeAco;
+  const bool aco = mode != kModeLem;
+  const bool tour = mode == kModeAcoTour;
   Planes src = h->user, dst = h->shadow;
   int chunk[64];
   int done = 0;
@@ -203,6 +217,8 @@ int run_steps(sim_handle* h, int mode, int32_t nsteps, hipStream_t s, hipEvent_t
       S.code_out = dst.code;
       S.id_out = dst.id;
       S.tau_out = aco ? dst.tau : nullptr;
+      S.tour_in = tour ? src.tour : nullptr;
+      S.tour_out = tour ? dst.tour : nullptr;
       S.tile_stats = h->stats;
       const bool last = done + chunk[j] == nsteps;
       if (ev) (void)hipEventRecord(ev[0], s);
@@ -224,7 +240,7 @@ int run_steps(sim_handle* h, int mode, int32_t nsteps, hipStream_t s, hipEvent_t
   }
   if (src.code != h->user.code) {  // odd number of launches: state is in the shadow planes
     if (ev) (void)hipEventRecord(ev[0], s);
-    PEDSIM_HIP(copy_planes(h->user, src, cells, aco, s));
+    PEDSIM_HIP(copy_planes(h->user, src, cells, aco, tour ? (size_t)h->agents : 0, s));
     if (ev) {
       (void)hipEventRecord(ev[1], s);
       PEDSIM_HIP(hipEventSynchronize(ev[1]));
@@ -251,6 +267,7 @@ const char* sim_strerror(int code) {
     case SIM_EHIP: return "HIP runtime error";
     case SIM_ENOTAU: return "ACO step needs pheromone planes";
     case SIM_EFULL: return "no free batch slot";
+    case SIM_ENOTOUR: return "tour step needs an attached tour array";
     default: return "unknown error";
   }
 }
@@ -274,7 +291,8 @@ int sim_create(const sim_params* p, uint8_t* d_code, uint32_t* d_id, float* d_ta
   hipStream_t s = (hipStream_t)stream;
   uint8_t* scratch = (uint8_t*)d_scratch;
   const size_t cells = (size_t)p->W * (size_t)p->H;
-  e = validate_state(p, d_code, d_id, d_tau, scratch, L, s);
+  uint64_t agents = 0;
+  e = validate_state(p, d_code, d_id, d_tau, scratch, L, s, &agents);
   if (e) return e;
   unsigned long long* totals = (unsigned long long*)(scratch + L.totals);
 
@@ -287,9 +305,11 @@ int sim_create(const sim_params* p, uint8_t* d_code, uint32_t* d_id, float* d_ta
   h->stats_cap = L.stats_cap;
   h->totals = totals;
   h->t = p->step0;
+  h->agents = agents;
   h->base = base_scenario(p);
-  h->tiling[kModeLem] = default_tiling(false, cells);
-  h->tiling[kModeAco] = default_tiling(true, cells);
+  h->tiling[kModeLem] = default_tiling(kModeLem, cells);
+  h->tiling[kModeAco] = default_tiling(kModeAco, cells);
+  h->tiling[kModeAcoTour] = default_tiling(kModeAcoTour, cells);
   const hipError_t e2 = launch_count(d_code, p->W, p->H, p->cross_a, p->cross_b, h->stats, &h->stats_entries, s);
   if (e2 != hipSuccess) {
     delete h;
@@ -299,9 +319,18 @@ int sim_create(const sim_params* p, uint8_t* d_code, uint32_t* d_id, float* d_ta
   return SIM_OK;
 }
 
+// SIM_OK if `mode` can step on h now.
+static int mode_ready(sim_handle* h, int mode) {
+  if (mode != kModeLem && mode != kModeAco && mode != kModeAcoTour) return SIM_EINVAL;
+  if (mode != kModeLem && !h->user.tau) return SIM_ENOTAU;
+  if (mode == kModeAcoTour && h->agents > 0 && !h->user.tour) return SIM_ENOTOUR;
+  return SIM_OK;
+}
+
 static int step_mode(sim_handle* h, int mode, int32_t nsteps, void* stream) {
   if (!h || nsteps < 0) return SIM_EINVAL;
-  if (mode == kModeAco && !h->user.tau) return SIM_ENOTAU;
+  const int e = mode_ready(h, mode);
+  if (e) return e;
   return run_steps(h, mode, nsteps, (hipStream_t)stream, nullptr, nullptr, nullptr);
 }
 
@@ -309,11 +338,33 @@ int sim_step_lem(sim_handle* h, int32_t nsteps, void* stream) { return step_mode
 
 int sim_step_aco(sim_handle* h, int32_t nsteps, void* stream) { return step_mode(h, kModeAco, nsteps, stream); }
 
+int sim_step_aco_tour(sim_handle* h, int32_t nsteps, void* stream) {
+  return step_mode(h, kModeAcoTour, nsteps, stream);
+}
+
+int sim_attach_tour(sim_handle* h, float* d_tour, float* d_tour_shadow, void* stream) {
+  if (!h) return SIM_EINVAL;
+  if (h->agents > 0 && (!d_tour || !d_tour_shadow || d_tour == d_tour_shadow)) return SIM_EINVAL;
+  if (h->agents > 0) {
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* counters = h->totals + kTileStatFields;
+    unsigned long long host_counters[3];
+    PEDSIM_HIP(hipMemsetAsync(counters, 0, 3 * sizeof(unsigned long long), s));
+    PEDSIM_HIP(launch_validate_values(d_tour, (size_t)h->agents, counters, s));
+    PEDSIM_HIP(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s));
+    PEDSIM_HIP(hipStreamSynchronize(s));
+    if (host_counters[2]) return SIM_ESTATE;
+  }
+  h->user.tour = d_tour;
+  h->shadow.tour = d_tour_shadow;
+  return SIM_OK;
+}
+
 int sim_set_tiling(sim_handle* h, int32_t mode, int32_t nw, int32_t rows, int32_t steps_per_launch,
                    int32_t threads) {
-  if (!h || (mode != kModeLem && mode != kModeAco)) return SIM_EINVAL;
+  if (!h || (mode != kModeLem && mode != kModeAco && mode != kModeAcoTour)) return SIM_EINVAL;
   const Tiling tl{nw, rows, steps_per_launch, threads};
-  if (!tiling_valid(tl, mode == kModeAco, max_dynamic_lds())) return SIM_EINVAL;
+  if (!tiling_valid(tl, mode, max_dynamic_lds())) return SIM_EINVAL;
   Scenario S = h->base;
   set_geometry(S, tl);
   if (S.tiles_x * S.tiles_y > h->stats_cap) return SIM_EINVAL;
@@ -322,7 +373,7 @@ int sim_set_tiling(sim_handle* h, int32_t mode, int32_t nw, int32_t rows, int32_
 }
 
 int sim_get_tiling(sim_handle* h, int32_t mode, int32_t out[4]) {
-  if (!h || !out || (mode != kModeLem && mode != kModeAco)) return SIM_EINVAL;
+  if (!h || !out || (mode != kModeLem && mode != kModeAco && mode != kModeAcoTour)) return SIM_EINVAL;
   const Tiling& tl = h->tiling[mode];
   out[0] = tl.nw;
   out[1] = tl.rows;
@@ -361,8 +412,8 @@ int sim_read_state(sim_handle* h, uint8_t* code, uint32_t* id, float* tau, void*
 int sim_step_timed(sim_handle* h, int32_t mode, int32_t nsteps, void* stream, double* kernel_ms,
                    int64_t* launches, int32_t max_kinds) {
   if (!h || nsteps < 0 || !kernel_ms || !launches || max_kinds < 2) return SIM_EINVAL;
-  if (mode != kModeLem && mode != kModeAco) return SIM_EINVAL;
-  if (mode == kModeAco && !h->user.tau) return SIM_ENOTAU;
+  const int ready = mode_ready(h, mode);
+  if (ready) return ready;
   hipEvent_t ev[2];
   PEDSIM_HIP(hipEventCreate(&ev[0]));
   const hipError_t e1 = hipEventCreate(&ev[1]);

@@ -13,6 +13,7 @@ namespace pedsim {
 
 constexpr int kModeLem = 0;
 constexpr int kModeAco = 1;
+constexpr int kModeAcoTour = 2;  // ACO with the tour matrix and eq. 5's deposit
 
 // Tiling of one scenario: regions of `rows` rows advanced `steps` steps per
 // launch (halo 3*steps), `threads` per workgroup. nw = 1 or 2 selects the
@@ -33,8 +34,11 @@ constexpr int kMinInteriorY = 8;
 inline bool rows_engine(const Tiling& tl) { return tl.nw == 0 || tl.nw == 3; }
 inline bool rows_stream(const Tiling& tl) { return tl.nw == 3; }
 inline int region_cols(const Tiling& tl) { return rows_engine(tl) ? 64 : 64 * tl.nw; }
-size_t tile_lds_bytes(const Tiling& tl, bool aco);
-bool tiling_valid(const Tiling& tl, bool aco, int max_lds);
+// LDS of one workgroup for `mode`; a tiling is valid for a mode when its
+// shape is allowed, fits max_lds, and (tour variant) uses the row-lane engine
+// with the pheromone staged in LDS (nw = 0).
+size_t tile_lds_bytes(const Tiling& tl, int mode);
+bool tiling_valid(const Tiling& tl, int mode, int max_lds);
 
 // One launch of the tile engine over every tile of S.
 hipError_t launch_tiles(const Scenario& S, const Tiling& tl, int mode, uint64_t t0, int steps, int last,
@@ -50,6 +54,8 @@ hipError_t launch_validate(const uint8_t* code, const uint32_t* id, const float*
                            unsigned long long* counters, hipStream_t s);
 hipError_t launch_validate_ids(const uint32_t* id, size_t cells, uint32_t n, uint32_t* bitmap,
                                unsigned long long* counters, hipStream_t s);
+// counters[2] |= 1 if any of the n values is negative, NaN or infinite.
+hipError_t launch_validate_values(const float* v, size_t n, unsigned long long* counters, hipStream_t s);
 
 int max_dynamic_lds();
 
@@ -67,6 +73,7 @@ struct Planes {
   uint8_t* code;
   uint32_t* id;
   float* tau;
+  float* tour = nullptr;  // tour variant: one float per agent
 };
 
 // Per-scenario scratch: shadow planes (code, id, both pheromone planes),
@@ -90,7 +97,7 @@ int check_params(const sim_params* p);
 Scenario base_scenario(const sim_params* p);
 void set_geometry(Scenario& S, const Tiling& tl);
 int validate_state(const sim_params* p, const uint8_t* d_code, const uint32_t* d_id, const float* d_tau,
-                   uint8_t* scratch, const ScratchLayout& L, hipStream_t s);
+                   uint8_t* scratch, const ScratchLayout& L, hipStream_t s, uint64_t* agents = nullptr);
 
 }  // namespace pedsim
 

@@ -32,19 +32,21 @@ __global__ __launch_bounds__(kRowsMaxThreads, kRowsMinWavesPerSimd) void tile_ro
                                   last != 0);
 }
 
-size_t tile_lds_bytes(const Tiling& tl, bool aco) {
-  if (rows_engine(tl)) return RowsLayout{tl.rows, tl.steps, aco, rows_stream(tl)}.bytes();
+size_t tile_lds_bytes(const Tiling& tl, int mode) {
+  const bool aco = mode != kModeLem;
+  if (rows_engine(tl)) return RowsLayout{tl.rows, tl.steps, aco, rows_stream(tl), mode == kModeAcoTour}.bytes();
   return tl.nw == 1 ? Layout<1>{tl.rows, aco}.bytes() : Layout<2>{tl.rows, aco}.bytes();
 }
 
-bool tiling_valid(const Tiling& tl, bool aco, int max_lds) {
+bool tiling_valid(const Tiling& tl, int mode, int max_lds) {
   if (tl.nw < 0 || tl.nw > 3) return false;
+  if (mode == kModeAcoTour && tl.nw != 0) return false;
   if (rows_engine(tl) && (tl.rows > kRowsMaxRows || tl.steps > kRowsMaxSteps || tl.threads > kRowsMaxThreads))
     return false;
   if (tl.steps < 1 || tl.threads < 64 || tl.threads > 1024 || tl.threads % 64) return false;
   if (tl.rows < 1 || tl.rows > 1023) return false;
   if (region_cols(tl) - 6 * tl.steps < kMinInteriorX || tl.rows - 6 * tl.steps < kMinInteriorY) return false;
-  return tile_lds_bytes(tl, aco) <= (size_t)max_lds;
+  return tile_lds_bytes(tl, mode) <= (size_t)max_lds;
 }
 
 int max_dynamic_lds() {
@@ -77,7 +79,7 @@ static hipError_t launch_one(const Scenario& S, const Tiling& tl, uint64_t t0, i
 
 template <int MODE, bool STREAM>
 static hipError_t launch_rows(const Scenario& S, const Tiling& tl, uint64_t t0, int steps, int last, hipStream_t s) {
-  const size_t lds = RowsLayout{tl.rows, tl.steps, MODE == kModeAco, STREAM}.bytes();
+  const size_t lds = RowsLayout{tl.rows, tl.steps, MODE != kModeLem, STREAM, MODE == kModeAcoTour}.bytes();
   static bool attr_done = false;
   if (!attr_done) {
     (void)hipFuncSetAttribute((const void*)tile_rows_kernel<MODE, STREAM>,
@@ -93,6 +95,10 @@ static hipError_t launch_rows(const Scenario& S, const Tiling& tl, uint64_t t0, 
 
 hipError_t launch_tiles(const Scenario& S, const Tiling& tl, int mode, uint64_t t0, int steps, int last,
                         hipStream_t s) {
+  if (mode == kModeAcoTour) {
+    if (tl.nw != 0) return hipErrorInvalidValue;
+    return launch_rows<kModeAcoTour, false>(S, tl, t0, steps, last, s);
+  }
   if (rows_stream(tl))
     return mode == kModeLem ? launch_rows<kModeLem, true>(S, tl, t0, steps, last, s)
                             : launch_rows<kModeAco, true>(S, tl, t0, steps, last, s);
@@ -214,6 +220,24 @@ hipError_t launch_validate(const uint8_t* code, const uint32_t* id, const float*
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   validate_cells_kernel<<<blocks, 256, 0, s>>>(code, id, tau, cells, counters);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void validate_values_kernel(const float* v, size_t n,
+                                                              unsigned long long* counters) {
+  unsigned bad = 0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const float x = v[i];
+    if (!(x >= 0.0f && x <= 3.402823466e38f)) bad = 1;
+  }
+  if (bad) atomicOr(&counters[2], 1ull);
+}
+
+hipError_t launch_validate_values(const float* v, size_t n, unsigned long long* counters, hipStream_t s) {
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  validate_values_kernel<<<blocks, 256, 0, s>>>(v, n, counters);
   return hipGetLastError();
 }
 

@@ -78,6 +78,8 @@ struct Scenario {
   uint8_t* code_out;
   uint32_t* id_out;
   float* tau_out;
+  const float* tour_in;  // tour variant: tour length per agent (index = agent number), else nullptr
+  float* tour_out;
   uint32_t* tile_stats;  // kTileStatFields per tile
   int W, H;
   int tiles_x, tiles_y;  // tile grid
@@ -85,6 +87,7 @@ struct Scenario {
   int halo;              // 3 * steps per launch
   uint32_t key0, key1;
   float keep, dtau, eta_diag, eta_lat;
+  float step_diag;  // tour variant: length of a diagonal move, fl(sqrt 2)
   int alpha;
   int cross_a, cross_b;
 };

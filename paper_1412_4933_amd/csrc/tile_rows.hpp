@@ -34,6 +34,15 @@
 // the group occupies it) applied s times, using the recorded occupancy,
 // exactly the per-step update of eq. 3 then eq. 4; it is evaluated where
 // needed (ACO candidates in step 2, every interior cell at write-back).
+//
+// Tour variant (MODE 2, eq. 5): a per-cell LDS copy of the tour length of the
+// agent standing there moves with the agent, grown by each move's length in
+// step 4. Deposits land only on entered cells, so step 4 also brings the
+// entered cell's value up to date (the evaporations since its last deposit in
+// this launch, then fl(dtau / L)) and stores it; every other evaluation only
+// owes the evaporations since a cell's last deposit, read off the history
+// (an agent of group g entered cell c in step u iff c was empty before step u
+// and holds g after it).
 #pragma once
 
 #include "rules.hpp"
@@ -52,7 +61,8 @@ constexpr int kRowsMinWavesPerSimd = 4;
 struct RowsLayout {
   int R, k;
   bool aco;
-  bool stream;  // pheromone read from HBM, tickets recomputed: no tick or tau arrays
+  bool stream;        // pheromone read from HBM, tickets recomputed: no tick or tau arrays
+  bool tour = false;  // tour variant: tour lengths per cell
   __host__ __device__ size_t hist() const { return 0; }                                  // [k+1][2][R] u64
   __host__ __device__ size_t wall() const { return hist() + (size_t)(k + 1) * 2 * R * 8; }  // [R] u64
   __host__ __device__ size_t side() const { return wall() + (size_t)R * 8; }             // [6][R] u64
@@ -64,7 +74,8 @@ struct RowsLayout {
   __host__ __device__ size_t tick() const { return ids() + (size_t)R * 256; }           // [R][64] u32
   __host__ __device__ size_t queue() const { return tick() + (stream ? 0 : (size_t)R * 256); }  // [R*64] u16
   __host__ __device__ size_t tau() const { return queue() + (size_t)R * 128; }          // [2][R][64] f32
-  __host__ __device__ size_t bytes() const { return tau() + (aco && !stream ? (size_t)R * 512 : 0); }
+  __host__ __device__ size_t tour_len() const { return tau() + (aco && !stream ? (size_t)R * 512 : 0); }  // [R][64] f32
+  __host__ __device__ size_t bytes() const { return tour_len() + (tour ? (size_t)R * 256 : 0); }
 };
 
 // Row r-1's value in lane r (0 in lane 0) / row r+1's value in lane r (0 in lane 63).
@@ -128,7 +139,7 @@ __device__ __forceinline__ void stage_issue(const Scenario& S, int R, int x0, in
     const size_t gi = in ? (size_t)gy * S.W + gx : 0;
     q.g[j] = in ? S.code_in[gi] : kWall;
     q.id[j] = in ? S.id_in[gi] : 0u;
-    if (MODE == 1) {
+    if (MODE != 0) {
       q.ta[j] = in ? S.tau_in[gi] : 0.0f;
       q.tb[j] = in ? S.tau_in[plane + gi] : 0.0f;
     }
@@ -143,7 +154,7 @@ __device__ __forceinline__ void stage_issue(const Scenario& S, int R, int x0, in
 template <int MODE, bool STREAM = false>
 __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k_max, int tx, int ty, int tile_index,
                                   uint64_t t0, int steps, bool last) {
-  const RowsLayout L{R, k_max, MODE == 1, STREAM};
+  const RowsLayout L{R, k_max, MODE != 0, STREAM, MODE == 2};
   uint64_t* hist = (uint64_t*)(smem + L.hist());
   uint64_t* wall_m = (uint64_t*)(smem + L.wall());
   uint64_t* side = (uint64_t*)(smem + L.side());
@@ -156,6 +167,7 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
   uint16_t* queue = (uint16_t*)(smem + L.queue());
   float* tau_a = (float*)(smem + L.tau());
   float* tau_b = tau_a + (size_t)R * 64;
+  float* tlen = (float*)(smem + L.tour_len());  // tour variant only
   // occupancy of group g (0 = A, 1 = B) at step s of the launch, row r
   auto H = [&](int s, int g, int r) -> uint64_t& { return hist[((size_t)s * 2 + g) * R + r]; };
 
@@ -188,9 +200,22 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
         wall_m[r] = bw;
       }
       ids[r * 64 + lane] = q.id[j];
-      if (MODE == 1 && !STREAM) {
+      if (MODE != 0 && !STREAM) {
         tau_a[r * 64 + lane] = q.ta[j];
         tau_b[r * 64 + lane] = q.tb[j];
+      }
+    }
+    if (MODE == 2) {  // the agents' tour lengths, gathered by agent number
+      float len[kStageRows];
+#pragma unroll
+      for (int j = 0; j < kStageRows; ++j) {
+        const int r = r0 + j * nwaves;
+        len[j] = (r < R && q.id[j] != 0u) ? S.tour_in[q.id[j] - 1u] : 0.0f;
+      }
+#pragma unroll
+      for (int j = 0; j < kStageRows; ++j) {
+        const int r = r0 + j * nwaves;
+        if (r < R) tlen[r * 64 + lane] = len[j];
       }
     }
   }
@@ -313,15 +338,31 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
               tau[2] = tp[ru * 64 + c];
               tau[3] = tp[rd * 64 + c];
             }
-            for (int u = 1; u <= s; ++u) {
-              const uint64_t hu = H(u, gp, ru), hd = H(u, gp, rd);
-              const unsigned ob = ((unsigned)(hu >> cfc) & 1u) | (((unsigned)(hd >> cfc) & 1u) << 1) |
-                                  (((unsigned)(hu >> c) & 1u) << 2) | (((unsigned)(hd >> c) & 1u) << 3);
+            if (MODE == 1) {
+              for (int u = 1; u <= s; ++u) {
+                const uint64_t hu = H(u, gp, ru), hd = H(u, gp, rd);
+                const unsigned ob = ((unsigned)(hu >> cfc) & 1u) | (((unsigned)(hd >> cfc) & 1u) << 1) |
+                                    (((unsigned)(hu >> c) & 1u) << 2) | (((unsigned)(hd >> c) & 1u) << 3);
 #pragma unroll
-              for (int j = 0; j < 4; ++j) {
-                tau[j] = S.keep * tau[j];
-                if ((ob >> j) & 1u) tau[j] = tau[j] + S.dtau;
+                for (int j = 0; j < 4; ++j) {
+                  tau[j] = S.keep * tau[j];
+                  if ((ob >> j) & 1u) tau[j] = tau[j] + S.dtau;
+                }
               }
+            } else {  // the LDS value is current through the cell's last deposit
+              int owed[4] = {s, s, s, s};
+              for (int u = 0; u < s; ++u) {
+                const uint64_t nu = H(u + 1, gp, ru) & ~(H(u, 0, ru) | H(u, 1, ru));
+                const uint64_t nd = H(u + 1, gp, rd) & ~(H(u, 0, rd) | H(u, 1, rd));
+                const unsigned ob = ((unsigned)(nu >> cfc) & 1u) | (((unsigned)(nd >> cfc) & 1u) << 1) |
+                                    (((unsigned)(nu >> c) & 1u) << 2) | (((unsigned)(nd >> c) & 1u) << 3);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                  if ((ob >> j) & 1u) owed[j] = s - 1 - u;
+              }
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                for (int i = 0; i < owed[j]; ++i) tau[j] = S.keep * tau[j];
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j)
@@ -411,6 +452,23 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
           src_id = ids[(r + dir_dr(best)) * 64 + c + dir_dc(best)];
         }
         ids[r * 64 + c] = src_id;
+        if (MODE == 2) {  // the tour grows by the move's length; eq. 5's deposit on the entered cell
+          const int sr = r + dir_dr(best), sc = c + dir_dc(best);
+          const bool diagonal = best >= 2 && best <= 5;
+          const float len = tlen[sr * 64 + sc] + (diagonal ? S.step_diag : 1.0f);
+          tlen[r * 64 + c] = len;
+          const bool ga = best == 0 || best == 2 || best == 3 || (best >= 6 && ((H(s, 0, sr) >> sc) & 1ull));
+          const int gp = ga ? 0 : 1;
+          float* tp = ga ? tau_a : tau_b;
+          int owed = s + 1;  // evaporations since the cell's last deposit, this step's included
+          for (int u = 0; u < s; ++u) {
+            const uint64_t entered = H(u + 1, gp, r) & ~(H(u, 0, r) | H(u, 1, r));
+            if ((entered >> c) & 1ull) owed = s - u;
+          }
+          float v = tp[r * 64 + c];
+          for (int i = 0; i < owed; ++i) v = S.keep * v;
+          tp[r * 64 + c] = v + S.dtau / len;
+        }
       }
       __syncthreads();
     }
@@ -449,7 +507,7 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
   for (int r0 = h + wave; r0 < R - h; r0 += nwaves * kWriteRows) {
     uint64_t ra[kWriteRows], rb[kWriteRows], rw[kWriteRows], rm[kWriteRows];
     uint32_t idv[kWriteRows], hist_a[kWriteRows], hist_b[kWriteRows];
-    float va[kWriteRows], vb[kWriteRows];
+    float va[kWriteRows], vb[kWriteRows], tl[kWriteRows];
     int rr[kWriteRows];
 #pragma unroll
     for (int j = 0; j < kWriteRows; ++j) {
@@ -462,6 +520,11 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
       idv[j] = ids[rr[j] * 64 + c];
       hist_a[j] = 0u;
       hist_b[j] = 0u;
+      if (MODE == 2) {
+        va[j] = tau_a[rr[j] * 64 + c];
+        vb[j] = tau_b[rr[j] * 64 + c];
+        tl[j] = tlen[rr[j] * 64 + c];
+      }
       if (MODE == 1) {
         if (STREAM) {  // from HBM (interior cells only; index 0 stands in for the rest)
           const int gy = y0 + rr[j];
@@ -481,6 +544,16 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
         for (int j = 0; j < kWriteRows; ++j) {
           hist_a[j] |= (uint32_t)((H(u, 0, rr[j]) >> c) & 1ull) << u;
           hist_b[j] |= (uint32_t)((H(u, 1, rr[j]) >> c) & 1ull) << u;
+        }
+      }
+    }
+    if (MODE == 2) {  // bit u: an agent of the group entered the cell in step u
+      for (int u = 0; u < steps; ++u) {
+#pragma unroll
+        for (int j = 0; j < kWriteRows; ++j) {
+          const uint64_t before = H(u, 0, rr[j]) | H(u, 1, rr[j]);
+          hist_a[j] |= (uint32_t)(((H(u + 1, 0, rr[j]) & ~before) >> c) & 1ull) << u;
+          hist_b[j] |= (uint32_t)(((H(u + 1, 1, rr[j]) & ~before) >> c) & 1ull) << u;
         }
       }
     }
@@ -508,6 +581,16 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
           }
           S.tau_out[gi] = a;
           S.tau_out[plane + gi] = b;
+        }
+        if (MODE == 2) {  // evaporations owed since each plane's last deposit
+          const int oa = hist_a[j] ? steps - 1 - (31 - __clz((int)hist_a[j])) : steps;
+          const int ob = hist_b[j] ? steps - 1 - (31 - __clz((int)hist_b[j])) : steps;
+          float a = va[j], b = vb[j];
+          for (int i = 0; i < oa; ++i) a = S.keep * a;
+          for (int i = 0; i < ob; ++i) b = S.keep * b;
+          S.tau_out[gi] = a;
+          S.tau_out[plane + gi] = b;
+          if (g == kGroupA || g == kGroupB) S.tour_out[idv[j] - 1u] = tl[j];
         }
       }
       if (last) {

@@ -18,7 +18,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpedsim.so")
 
 SIM_OK, SIM_EINVAL, SIM_ESTATE, SIM_ESCRATCH, SIM_EHIP, SIM_ENOTAU, SIM_EFULL = 0, -1, -2, -3, -4, -5, -6
-SIM_MODE_LEM, SIM_MODE_ACO = 0, 1
+SIM_ENOTOUR = -7
+SIM_MODE_LEM, SIM_MODE_ACO, SIM_MODE_ACO_TOUR = 0, 1, 2
 
 
 class SimError(RuntimeError):
@@ -72,6 +73,8 @@ def lib() -> ctypes.CDLL:
         L.sim_create.argtypes = [P(SimParams), vp, vp, vp, vp, sz, vp, P(vp)]
         L.sim_step_lem.argtypes = [vp, i32, vp]
         L.sim_step_aco.argtypes = [vp, i32, vp]
+        L.sim_step_aco_tour.argtypes = [vp, i32, vp]
+        L.sim_attach_tour.argtypes = [vp, vp, vp, vp]
         L.sim_stats.argtypes = [vp, P(SimStats), vp]
         L.sim_read_state.argtypes = [vp, vp, vp, vp, vp]
         L.sim_step_timed.argtypes = [vp, i32, i32, vp, P(ctypes.c_double), P(ctypes.c_int64), i32]
@@ -85,7 +88,7 @@ def lib() -> ctypes.CDLL:
         L.sim_destroy.argtypes = [vp]
         L.sim_destroy.restype = None
         for name in ("sim_scratch_bytes", "sim_create", "sim_step_lem", "sim_step_aco",
-                     "sim_stats", "sim_read_state"):
+                     "sim_step_aco_tour", "sim_attach_tour", "sim_stats", "sim_read_state"):
             getattr(L, name).restype = ctypes.c_int
         _bind_batch(L)
         _lib = L
@@ -159,6 +162,14 @@ def sim_step_lem(h, nsteps: int, stream=None) -> None:
 
 def sim_step_aco(h, nsteps: int, stream=None) -> None:
     _check(lib().sim_step_aco(h, int(nsteps), _stream(stream)), "sim_step_aco")
+
+
+def sim_attach_tour(h, tour, tour_shadow, stream=None) -> None:
+    _check(lib().sim_attach_tour(h, _ptr(tour), _ptr(tour_shadow), _stream(stream)), "sim_attach_tour")
+
+
+def sim_step_aco_tour(h, nsteps: int, stream=None) -> None:
+    _check(lib().sim_step_aco_tour(h, int(nsteps), _stream(stream)), "sim_step_aco_tour")
 
 
 def sim_stats(h, stream=None) -> dict:
@@ -290,13 +301,31 @@ class Sim:
         torch.cuda.synchronize(self.device)
         self.h = sim_create(self.params, self.code, self.ids, self.tau, self.scratch, nbytes,
                             stream)
+        # tour variant: the tour matrix (one float per agent) and its ping-pong half
+        self.tour = self.tour_shadow = None
+        if scenario.mode == SIM_MODE_ACO_TOUR or getattr(scenario, "tour", None) is not None:
+            n = int(scenario.ids.max()) if scenario.ids.size else 0
+            t0 = scenario.tour if getattr(scenario, "tour", None) is not None else np.zeros(n, np.float32)
+            self.tour = torch.from_numpy(np.ascontiguousarray(t0, dtype=np.float32)).to(self.device)
+            self.tour_shadow = torch.empty_like(self.tour)
+            torch.cuda.synchronize(self.device)
+            sim_attach_tour(self.h, self.tour if n else None, self.tour_shadow if n else None,
+                            stream)
 
     def step(self, nsteps: int, mode: Optional[int] = None) -> None:
         mode = self.scenario.mode if mode is None else mode
         if mode == SIM_MODE_LEM:
             sim_step_lem(self.h, nsteps, self.stream)
+        elif mode == SIM_MODE_ACO_TOUR:
+            sim_step_aco_tour(self.h, nsteps, self.stream)
         else:
             sim_step_aco(self.h, nsteps, self.stream)
+
+    def tour_lengths(self) -> np.ndarray:
+        """The tour matrix (float32 [N], index = agent number) on the host."""
+        s = self.stream if self.stream is not None else self.torch.cuda.current_stream(self.device)
+        s.synchronize()
+        return self.tour.cpu().numpy()
 
     def stats(self) -> dict:
         return sim_stats(self.h, self.stream)

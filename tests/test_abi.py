@@ -23,7 +23,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("sim_create", "sim_step_lem", "sim_step_aco", "sim_stats", "sim_scratch_bytes",
-              "sim_read_state", "sim_destroy", "sim_strerror"):
+              "sim_read_state", "sim_destroy", "sim_strerror", "sim_attach_tour",
+              "sim_step_aco_tour"):
         assert n in names
 
 
@@ -34,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_strerror_names_every_code():
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert pedsim.sim_strerror(code) not in ("", "unknown error")
     assert pedsim.sim_strerror(-99) == "unknown error"
 
@@ -121,3 +122,9 @@ def test_library_loads_after_torch_runtime():
     import sys
     pedsim.lib()
     assert "torch" in sys.modules
+
+
+def test_tour_calls_reject_null_handle():
+    L = pedsim.lib()
+    assert L.sim_step_aco_tour(None, 1, None) == pedsim.SIM_EINVAL
+    assert L.sim_attach_tour(None, None, None, None) == pedsim.SIM_EINVAL
