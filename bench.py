@@ -29,11 +29,14 @@ WORKLOADS = {
     "served": ("served_requests", "Poisson stream of scenarios drawn like the batch, 200-2000 steps each, "
                "continuous batching under an HBM budget"),
     "lem_200x100": ("lem_200x100", "LEM 200x100, 1,000 agents per group, 500 steps"),
+    "aco_tour_1024x512": ("aco_tour_1024x512", "ACO tour variant (eq. 5 deposits, tour matrix) 1024x512, "
+                          "50,000 agents per group (100K), 2,000 steps"),
     "stress_aco_4096x2048": ("stress_4096x2048", "ACO 4096x2048, 5% obstacles, 1M agents"),
     "stress_lem_4096x2048": ("stress_4096x2048", "LEM 4096x2048, 5% obstacles, 1M agents"),
 }
 # workloads run by the single-scenario path
-PLAIN = ("aco_1024x512", "lem_200x100", "stress_aco_4096x2048", "stress_lem_4096x2048")
+PLAIN = ("aco_1024x512", "aco_tour_1024x512", "lem_200x100", "stress_aco_4096x2048", "stress_lem_4096x2048")
+MODE_NAMES = {0: "LEM", 1: "ACO", 2: "ACO tour variant"}
 
 
 def log(*a):
@@ -51,8 +54,9 @@ def algorithmic_bytes_per_step(mode: int, cells: int, agents: int) -> int:
     """Bytes one step of the method must move (lower bound; the few bytes of
     the agents that actually move are left out): every code byte is read,
     every agent's id is read, and for ACO both pheromone planes are read and
-    written (8 B read + 8 B write per cell)."""
-    return cells * (1 + (16 if mode == 1 else 0)) + agents * 4
+    written (8 B read + 8 B write per cell); the tour variant also reads and
+    writes every agent's tour length (4 B + 4 B per agent)."""
+    return cells * (1 + (16 if mode != 0 else 0)) + agents * (4 + (8 if mode == 2 else 0))
 
 
 def kernel_source_digest() -> str:
@@ -322,7 +326,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+u32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload][1], "grid": f"{scn.W}x{scn.H}",
-                   "agents": agents, "mode": "ACO" if mode == 1 else "LEM", "seed": scn.seed},
+                   "agents": agents, "mode": MODE_NAMES[mode], "seed": scn.seed},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "served": served,

@@ -126,13 +126,14 @@ namespace {
 // fits the device's LDS is used.
 // The tour variant runs on the row-lane engine with the pheromone in LDS
 // (its deposits depend on per-move tour lengths, so they are applied in LDS
-// as they happen).
+// as they happen); its extra per-cell tour lengths make the 56-row shape too
+// big for two workgroups per compute unit, so medium grids use 48 rows.
 Tiling default_tiling(int mode, size_t cells) {
   static const Tiling tiny_opts[] = {{0, 48, 6, 512}, {0, 32, 4, 256}, {1, 32, 1, 256}};
   static const Tiling small_opts[] = {{0, 56, 4, 512}, {0, 48, 3, 512}, {1, 32, 1, 256}};
   static const Tiling large_opts[] = {{3, 48, 2, 256}, {0, 48, 2, 512}, {1, 32, 1, 256}};
   static const Tiling tour_tiny[] = {{0, 48, 6, 512}, {0, 32, 4, 256}, {0, 32, 1, 256}};
-  static const Tiling tour_small[] = {{0, 56, 4, 512}, {0, 48, 3, 512}, {0, 32, 1, 256}};
+  static const Tiling tour_small[] = {{0, 48, 3, 512}, {0, 40, 3, 512}, {0, 32, 1, 256}};
   static const Tiling tour_large[] = {{0, 48, 2, 512}, {0, 40, 2, 256}, {0, 32, 1, 256}};
   const int size = cells < ((size_t)1 << 18) ? 0 : (cells < ((size_t)2 << 20) ? 1 : 2);
   const Tiling* const plain[3] = {tiny_opts, small_opts, large_opts};

@@ -360,9 +360,11 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
                 for (int j = 0; j < 4; ++j)
                   if ((ob >> j) & 1u) owed[j] = s - 1 - u;
               }
+              for (int u = 0; u < s; ++u) {  // the owed evaporations are the last ones
 #pragma unroll
-              for (int j = 0; j < 4; ++j)
-                for (int i = 0; i < owed[j]; ++i) tau[j] = S.keep * tau[j];
+                for (int j = 0; j < 4; ++j)
+                  if (u >= s - owed[j]) tau[j] = S.keep * tau[j];
+              }
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j)
@@ -466,7 +468,8 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
             if ((entered >> c) & 1ull) owed = s - u;
           }
           float v = tp[r * 64 + c];
-          for (int i = 0; i < owed; ++i) v = S.keep * v;
+          for (int u = 0; u <= s; ++u)
+            if (u > s - owed) v = S.keep * v;
           tp[r * 64 + c] = v + S.dtau / len;
         }
       }
@@ -586,8 +589,10 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
           const int oa = hist_a[j] ? steps - 1 - (31 - __clz((int)hist_a[j])) : steps;
           const int ob = hist_b[j] ? steps - 1 - (31 - __clz((int)hist_b[j])) : steps;
           float a = va[j], b = vb[j];
-          for (int i = 0; i < oa; ++i) a = S.keep * a;
-          for (int i = 0; i < ob; ++i) b = S.keep * b;
+          for (int u = 0; u < steps; ++u) {  // the owed evaporations are the last ones
+            if (u >= steps - oa) a = S.keep * a;
+            if (u >= steps - ob) b = S.keep * b;
+          }
           S.tau_out[gi] = a;
           S.tau_out[plane + gi] = b;
           if (g == kGroupA || g == kGroupB) S.tour_out[idv[j] - 1u] = tl[j];

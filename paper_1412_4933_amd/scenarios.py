@@ -206,6 +206,24 @@ def stress_4096x2048(mode: int = MODE_ACO, seed: int = 1) -> Scenario:
                          steps=1000, obstacle_frac=0.05, with_tau=True)
 
 
+def paper_sweep(densities=range(1, 21), repeats: int = 10, steps: int = 25000,
+                modes=(MODE_LEM, MODE_ACO), size: int = 480) -> List[Scenario]:
+    """The population sweep of the paper's results (Sec. VI): a size x size
+    grid, 1,280 k agents per group for density k (2,560 k in all), each group
+    packed into the narrowest band that holds it (3 columns for k = 1), a
+    crossing line at the opposite group's band, `steps` steps, `repeats`
+    placements per density. LEM and ACO runs of one (k, repeat) share their
+    placement and random key (seed 100 k + repeat), so the comparison is
+    paired. Returns the scenarios ordered by (k, repeat, mode)."""
+    out = []
+    for k in densities:
+        for rep in range(repeats):
+            for mode in modes:
+                out.append(make_scenario(size, size, 1280 * k, 1280 * k, band_a=1, seed=100 * k + rep,
+                                         mode=mode, steps=steps))
+    return out
+
+
 def batch_shapes(count: int = 256, rng_seed: int = 0):
     """(W, H, N, band, mode) for a batch of independent scenarios: widths
     log-uniform in [64, 2048] rounded to even, H = W/2, populations log-uniform
