@@ -29,6 +29,7 @@ class OracleParams(ctypes.Structure):
         ("rho", ctypes.c_float), ("dtau", ctypes.c_float),
         ("alpha", ctypes.c_int32), ("beta", ctypes.c_int32),
         ("cross_a", ctypes.c_int32), ("cross_b", ctypes.c_int32),
+        ("neighbours", ctypes.c_int32),
     ]
 
 
@@ -94,14 +95,15 @@ def agent_words(seed: int, t: int, k: int):
 
 
 def lem_thresholds():
-    o = (ctypes.c_uint32 * 3)()
+    o = (ctypes.c_uint32 * 6)()
     lib().oracle_lem_thresholds(o)
     return tuple(int(v) for v in o)
 
 
 def heuristic_weights(beta: int):
-    """(eta^beta) for the forward, diagonal and lateral candidates."""
-    o = (ctypes.c_float * 3)()
+    """(eta^beta) for the forward, diagonal, lateral, backward and backward
+    diagonal candidates."""
+    o = (ctypes.c_float * 5)()
     lib().oracle_heuristic_weights(int(beta), o)
     return tuple(np.float32(v) for v in o)
 
@@ -114,7 +116,7 @@ class State:
 
     def __init__(self, code, ids, tau=None, *, seed: int, rho: float = 0.1,
                  dtau: float = 1.0, alpha: int = 1, beta: int = 2, cross_a: int = 1,
-                 cross_b: int = 1, t: int = 0, tour=None):
+                 cross_b: int = 1, t: int = 0, tour=None, neighbours: int = 5):
         self.code = np.ascontiguousarray(code, dtype=np.uint8).copy()
         self.ids = np.ascontiguousarray(ids, dtype=np.uint32).copy()
         self.H, self.W = self.code.shape
@@ -130,14 +132,14 @@ class State:
             self.tau = np.ascontiguousarray(tau, dtype=np.float32).copy()
             assert self.tau.shape == (2, self.H, self.W)
         self.p = OracleParams(self.W, self.H, seed, rho, dtau, alpha, beta, cross_a,
-                              cross_b)
+                              cross_b, neighbours)
         self.t = t
 
     @classmethod
     def from_scenario(cls, s) -> "State":
         return cls(s.code, s.ids, s.tau, seed=s.seed, rho=s.rho, dtau=s.dtau,
                    alpha=s.alpha, beta=s.beta, cross_a=s.cross_a, cross_b=s.cross_b,
-                   tour=getattr(s, "tour", None))
+                   tour=getattr(s, "tour", None), neighbours=getattr(s, "neighbours", 5))
 
     def _tau_ptrs(self, mode):
         if mode in (MODE_ACO, MODE_ACO_TOUR):

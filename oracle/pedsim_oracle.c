@@ -25,8 +25,10 @@
  *     heads -x; code 3 is a wall; outside the grid counts as wall.
  *   - candidates: forward F=(x+d,y), forward diagonals FD-=(x+d,y-1) and
  *     FD+=(x+d,y+1), laterals L-=(x,y-1) and L+=(x,y+1); staying is implicit.
- *     The paper allows all eight neighbours (Sec. III); backward cells are
- *     left out here.
+ *     With neighbours = 8 (the paper's full neighbourhood, Sec. III) also
+ *     backward B=(x-d,y) and the backward diagonals BD-=(x-d,y-1) and
+ *     BD+=(x-d,y+1), ranked after the laterals (Sec. IV.b-c); otherwise the
+ *     backward cells are left out.
  *   - "empty" means code 0 in the snapshot of time t: a cell vacated in step
  *     t can only be entered in step t+1.
  *   - forward first: an empty F is taken without further calculation
@@ -35,17 +37,19 @@
  *     counter (agent k, t low word, t high word, 0) and key (seed low word,
  *     seed high word); words r0 = conflict ticket, r1 = choice, r2 = side bit.
  *   - distance table (constant, Sec. IV.a-b): squared distance from each
- *     candidate to the point two cells ahead: F 1, FD 2, L 5, so that F is
- *     nearest and the two diagonals tie (Sec. IV.b). eta = 1/D, and the
- *     heuristic weight eta^beta is the correctly rounded float of D2^(-beta/2).
+ *     candidate to the point two cells ahead: F 1, FD 2, L 5, B 9, BD 10, so
+ *     that F is nearest, the two diagonals tie (Sec. IV.b) and the backward
+ *     cells come last. eta = 1/D, and the heuristic weight eta^beta is the
+ *     correctly rounded float of D2^(-beta/2).
  *   - LEM (eq. 1, Sec. II.A and IV.c): the empty candidates are ranked by
  *     distance, the two members of a symmetric pair in an order drawn from
  *     bit 0 of r2 (set: the +y side first). z ~ N(0,1) from r1, negatives go
  *     to 0, the index is round-half-up(z) clamped to the last candidate:
  *     index = #{j : r1 >= T_j}, T_j = ceil(2^32 * Phi(j + 1/2)).
  *   - ACO (eq. 2 with alpha, beta, Sec. II.B and IV.c): weights
- *     w_i = tau_g(c_i)^alpha * eta_i^beta over [FD-, FD+, L-, L+] (0 when
- *     the candidate is not empty), tau_g the agent's own group's plane;
+ *     w_i = tau_g(c_i)^alpha * eta_i^beta over [FD-, FD+, L-, L+] (then
+ *     [B, BD-, BD+] with eight neighbours; 0 when the candidate is not
+ *     empty), tau_g the agent's own group's plane, summed left to right;
  *     roulette with u = (r1 >> 8) * 2^-24 against running float sums; when
  *     every weight is 0 the LEM rule is used with the same words.
  *   - conflict winner (Sec. IV.d picks one requester uniformly): the lowest
@@ -80,6 +84,9 @@
 #define O_REQ_FDP 3
 #define O_REQ_LM 4
 #define O_REQ_LP 5
+#define O_REQ_B 6
+#define O_REQ_BDM 7
+#define O_REQ_BDP 8
 
 typedef struct {
   int32_t W, H;
@@ -87,6 +94,7 @@ typedef struct {
   float rho, dtau;
   int32_t alpha, beta;
   int32_t cross_a, cross_b;
+  int32_t neighbours; /* 8: all eight neighbours; anything else: no backward cells */
 } oracle_params;
 
 /* ------------------------------------------------------------------------ */
@@ -138,32 +146,40 @@ static void agent_words(uint64_t seed, uint64_t t, uint32_t k, uint32_t w[4]) {
   oracle_philox4x32_10(ctr, key, w);
 }
 
-/* LEM thresholds T_j = ceil(2^32 * Phi(j + 1/2)), j = 0, 1, 2, with Phi the
+/* LEM thresholds T_j = ceil(2^32 * Phi(j + 1/2)), j = 0..5, with Phi the
  * standard normal CDF: Phi(0.5) = 0.69146246127..., Phi(1.5) = 0.93319279873...,
- * Phi(2.5) = 0.99379033467... */
-static const uint32_t lem_threshold[3] = {2969808658u, 4008032552u, 4268296987u};
+ * Phi(2.5) = 0.99379033467..., Phi(3.5) = 0.99976737092..., Phi(4.5) =
+ * 0.99999660232..., Phi(5.5) = 0.99999998101... */
+static const uint32_t lem_threshold[6] = {2969808658u, 4008032552u, 4268296987u,
+                                          4293968162u, 4294952704u, 4294967215u};
 
-void oracle_lem_thresholds(uint32_t out[3]) {
-  out[0] = lem_threshold[0];
-  out[1] = lem_threshold[1];
-  out[2] = lem_threshold[2];
+void oracle_lem_thresholds(uint32_t out[6]) {
+  int j;
+  for (j = 0; j < 6; ++j) out[j] = lem_threshold[j];
 }
 
 /* Squared distances from a candidate to the point two cells ahead. */
 #define D2_FORWARD 1.0
 #define D2_DIAGONAL 2.0
 #define D2_LATERAL 5.0
+#define D2_BACKWARD 9.0
+#define D2_BACK_DIAGONAL 10.0
 
 /* eta^beta = D2^(-beta/2), rounded to float. */
 static float heuristic_weight(double d2, int beta) {
   return (float)pow(d2, -0.5 * (double)beta);
 }
 
-void oracle_heuristic_weights(int32_t beta, float out[3]) {
+void oracle_heuristic_weights(int32_t beta, float out[5]) {
   out[0] = heuristic_weight(D2_FORWARD, beta);
   out[1] = heuristic_weight(D2_DIAGONAL, beta);
   out[2] = heuristic_weight(D2_LATERAL, beta);
+  out[3] = heuristic_weight(D2_BACKWARD, beta);
+  out[4] = heuristic_weight(D2_BACK_DIAGONAL, beta);
 }
+
+/* Number of side candidates (all but F): 4, or 7 with eight neighbours. */
+static int side_count(const oracle_params *p) { return p->neighbours == 8 ? 7 : 4; }
 
 static int inside(const oracle_params *p, int x, int y) {
   return x >= 0 && x < p->W && y >= 0 && y < p->H;
@@ -186,38 +202,45 @@ static void target_of(int r, int x, int y, int d, int *tx, int *ty) {
     case O_REQ_FDP: *tx = x + d; *ty = y + 1; break;
     case O_REQ_LM: *ty = y - 1; break;
     case O_REQ_LP: *ty = y + 1; break;
+    case O_REQ_B: *tx = x - d; break;
+    case O_REQ_BDM: *tx = x - d; *ty = y - 1; break;
+    case O_REQ_BDP: *tx = x - d; *ty = y + 1; break;
     default: break;
   }
 }
 
 /* LEM choice among the side candidates, eq. (1) with the normal draw.
- * avail[0..3] refer to FD-, FD+, L-, L+. */
-static int lem_choice(const int avail[4], uint32_t r1, uint32_t r2) {
-  static const int minus_first[4] = {O_REQ_FDM, O_REQ_FDP, O_REQ_LM, O_REQ_LP};
-  static const int plus_first[4] = {O_REQ_FDP, O_REQ_FDM, O_REQ_LP, O_REQ_LM};
+ * avail[i] refers to request O_REQ_FDM + i (FD-, FD+, L-, L+, B, BD-, BD+);
+ * the first `sides` of them exist. */
+static int lem_choice(const int avail[7], int sides, uint32_t r1, uint32_t r2) {
+  static const int minus_first[7] = {O_REQ_FDM, O_REQ_FDP, O_REQ_LM, O_REQ_LP,
+                                     O_REQ_B, O_REQ_BDM, O_REQ_BDP};
+  static const int plus_first[7] = {O_REQ_FDP, O_REQ_FDM, O_REQ_LP, O_REQ_LM,
+                                    O_REQ_B, O_REQ_BDP, O_REQ_BDM};
   const int *order = (r2 & 1u) ? plus_first : minus_first;
-  int ranked[4];
+  int ranked[7];
   int n = 0, i, index;
-  for (i = 0; i < 4; ++i) {
+  for (i = 0; i < sides; ++i) {
     int r = order[i];
     if (avail[r - O_REQ_FDM]) ranked[n++] = r;
   }
   if (n == 0) return O_REQ_NONE;
   index = 0;
-  for (i = 0; i < 3; ++i)
+  for (i = 0; i < sides - 1; ++i)
     if (r1 >= lem_threshold[i]) index += 1;
   if (index > n - 1) index = n - 1;
   return ranked[index];
 }
 
 /* ACO choice among the side candidates, eq. (2): roulette on
- * tau^alpha * eta^beta. tau[0..3] is the group's pheromone on FD-, FD+, L-, L+. */
-static int aco_choice(const int avail[4], const float tau[4], float eta_diag,
-                      float eta_lat, int alpha, uint32_t r1, uint32_t r2) {
-  float w[4];
+ * tau^alpha * eta^beta. tau[i] is the group's pheromone on candidate i
+ * (FD-, FD+, L-, L+, B, BD-, BD+), eta[i] its heuristic weight. */
+static int aco_choice(const int avail[7], int sides, const float tau[7], const float eta[7],
+                      int alpha, uint32_t r1, uint32_t r2) {
+  float w[7];
   float sum, u, target, running;
   int i, last;
-  for (i = 0; i < 4; ++i) {
+  for (i = 0; i < sides; ++i) {
     if (avail[i]) {
       float power = 1.0f;
       int a;
@@ -225,20 +248,19 @@ static int aco_choice(const int avail[4], const float tau[4], float eta_diag,
         power = tau[i];
         for (a = 1; a < alpha; ++a) power = power * tau[i];
       }
-      w[i] = power * (i < 2 ? eta_diag : eta_lat);
+      w[i] = power * eta[i];
     } else {
       w[i] = 0.0f;
     }
   }
-  sum = w[0] + w[1];
-  sum = sum + w[2];
-  sum = sum + w[3];
-  if (sum == 0.0f) return lem_choice(avail, r1, r2);
+  sum = w[0];
+  for (i = 1; i < sides; ++i) sum = sum + w[i];
+  if (sum == 0.0f) return lem_choice(avail, sides, r1, r2);
   u = (float)(r1 >> 8) * 0x1p-24f;
   target = u * sum;
   running = 0.0f;
   last = -1;
-  for (i = 0; i < 4; ++i) {
+  for (i = 0; i < sides; ++i) {
     running = running + w[i];
     if (w[i] > 0.0f) {
       last = i;
@@ -251,28 +273,30 @@ static int aco_choice(const int avail[4], const float tau[4], float eta_diag,
 /* Request of the agent standing on (x, y) at step t. */
 static int request_of(const oracle_params *p, int mode, uint64_t t, const uint8_t *code,
                       const uint32_t *id, const float *tau_a, const float *tau_b,
-                      float eta_diag, float eta_lat, int x, int y) {
+                      const float eta[7], int x, int y) {
   size_t c = (size_t)y * (size_t)p->W + (size_t)x;
   int g = code[c];
   int d = heading(g);
-  int avail[4];
-  int side_x[4], side_y[4];
+  int sides = side_count(p);
+  int avail[7];
+  int side_x[7], side_y[7];
   uint32_t w[4];
-  int i;
+  int i, any = 0;
   if (free_cell(p, code, x + d, y)) return O_REQ_F;
-  for (i = 0; i < 4; ++i) {
+  for (i = 0; i < sides; ++i) {
     target_of(O_REQ_FDM + i, x, y, d, &side_x[i], &side_y[i]);
     avail[i] = free_cell(p, code, side_x[i], side_y[i]);
+    any = any || avail[i];
   }
-  if (!avail[0] && !avail[1] && !avail[2] && !avail[3]) return O_REQ_NONE;
+  if (!any) return O_REQ_NONE;
   agent_words(p->seed, t, id[c] - 1u, w);
-  if (mode == 0) return lem_choice(avail, w[1], w[2]);
+  if (mode == 0) return lem_choice(avail, sides, w[1], w[2]);
   {
     const float *plane = (g == O_A) ? tau_a : tau_b;
-    float tau[4];
-    for (i = 0; i < 4; ++i)
+    float tau[7];
+    for (i = 0; i < sides; ++i)
       tau[i] = avail[i] ? plane[(size_t)side_y[i] * (size_t)p->W + (size_t)side_x[i]] : 0.0f;
-    return aco_choice(avail, tau, eta_diag, eta_lat, p->alpha, w[1], w[2]);
+    return aco_choice(avail, sides, tau, eta, p->alpha, w[1], w[2]);
   }
 }
 
@@ -294,8 +318,7 @@ static int64_t step_any(const oracle_params *p, int32_t mode, uint64_t t, uint8_
   uint8_t *new_code = (uint8_t *)malloc(cells);
   uint32_t *new_id = (uint32_t *)malloc(cells * sizeof(uint32_t));
   uint8_t *entered = (uint8_t *)calloc(cells, 1); /* mode 2: group that entered the cell */
-  float eta_diag = heuristic_weight(D2_DIAGONAL, p->beta);
-  float eta_lat = heuristic_weight(D2_LATERAL, p->beta);
+  float eta[7];
   const float diagonal_step = (float)sqrt(2.0);
   int64_t moved = 0;
   int x, y;
@@ -306,6 +329,10 @@ static int64_t step_any(const oracle_params *p, int32_t mode, uint64_t t, uint8_
     free(entered);
     return -1;
   }
+  eta[0] = eta[1] = heuristic_weight(D2_DIAGONAL, p->beta);
+  eta[2] = eta[3] = heuristic_weight(D2_LATERAL, p->beta);
+  eta[4] = heuristic_weight(D2_BACKWARD, p->beta);
+  eta[5] = eta[6] = heuristic_weight(D2_BACK_DIAGONAL, p->beta);
   if (win_out) memset(win_out, 0, cells);
 
   /* 1. request, every agent on the snapshot of time t */
@@ -313,8 +340,7 @@ static int64_t step_any(const oracle_params *p, int32_t mode, uint64_t t, uint8_
     for (x = 0; x < W; ++x) {
       size_t c = (size_t)y * W + x;
       if (code[c] == O_A || code[c] == O_B)
-        req[c] = (uint8_t)request_of(p, mode, t, code, id, tau_a, tau_b, eta_diag,
-                                     eta_lat, x, y);
+        req[c] = (uint8_t)request_of(p, mode, t, code, id, tau_a, tau_b, eta, x, y);
     }
 
   /* 2.+3. resolve every cell empty at t, then commit into fresh planes */

@@ -37,18 +37,22 @@ def _phi(z):
 
 
 # ceil(2^32 * Phi(j + 1/2)); double precision is ample here because none of
-# the three products lies within 1e-6 of an integer.
-THRESHOLDS = [int(math.ceil(4294967296.0 * _phi(j + 0.5))) for j in range(3)]
+# the six products lies within 1e-6 of an integer.
+THRESHOLDS = [int(math.ceil(4294967296.0 * _phi(j + 0.5))) for j in range(6)]
 
-# candidate offsets (dx in units of the heading d, dy)
-CAND = {1: (1, 0), 2: (1, -1), 3: (1, 1), 4: (0, -1), 5: (0, 1)}
+# candidate offsets (dx in units of the heading d, dy); 6..8 are the backward
+# cells of the eight-neighbour set
+CAND = {1: (1, 0), 2: (1, -1), 3: (1, 1), 4: (0, -1), 5: (0, 1), 6: (-1, 0), 7: (-1, -1),
+        8: (-1, 1)}
+# squared distance to the point two cells ahead
+D2 = {2: 2, 3: 2, 4: 5, 5: 5, 6: 9, 7: 10, 8: 10}
 
 
 def _weight(d2, beta):
     return F32(float(d2) ** (-0.5 * beta))
 
 
-def step(code, ids, tau, *, mode, t, seed, rho, dtau, alpha, beta, tour=None):
+def step(code, ids, tau, *, mode, t, seed, rho, dtau, alpha, beta, tour=None, neighbours=5):
     """One step on copies; returns (code, ids, tau, req, moved), or with
     mode 2 (code, ids, tau, tour, req, moved)."""
     H, W = code.shape
@@ -64,12 +68,14 @@ def step(code, ids, tau, *, mode, t, seed, rho, dtau, alpha, beta, tour=None):
     def empty(x, y):
         return 0 <= x < W and 0 <= y < H and code[y, x] == 0
 
+    sides = (2, 3, 4, 5, 6, 7, 8) if neighbours == 8 else (2, 3, 4, 5)
+
     def lem(avail, r1, r2):
-        order = [3, 2, 5, 4] if (r2 & 1) else [2, 3, 4, 5]
-        ranked = [r for r in order if avail[r]]
+        order = [3, 2, 5, 4, 6, 8, 7] if (r2 & 1) else [2, 3, 4, 5, 6, 7, 8]
+        ranked = [r for r in order if r in avail and avail[r]]
         if not ranked:
             return 0
-        idx = sum(1 for th in THRESHOLDS if r1 >= th)
+        idx = sum(1 for th in THRESHOLDS[:len(sides) - 1] if r1 >= th)
         return ranked[min(idx, len(ranked) - 1)]
 
     req = np.zeros((H, W), dtype=np.uint8)
@@ -83,7 +89,7 @@ def step(code, ids, tau, *, mode, t, seed, rho, dtau, alpha, beta, tour=None):
                 req[y, x] = 1
                 continue
             avail = {}
-            for r in (2, 3, 4, 5):
+            for r in sides:
                 ox, oy = CAND[r]
                 avail[r] = empty(x + ox * d, y + oy)
             if not any(avail.values()):
@@ -94,7 +100,7 @@ def step(code, ids, tau, *, mode, t, seed, rho, dtau, alpha, beta, tour=None):
                 continue
             plane = tau[g - 1]
             ws = []
-            for r in (2, 3, 4, 5):
+            for r in sides:
                 if not avail[r]:
                     ws.append(F32(0.0))
                     continue
@@ -105,8 +111,10 @@ def step(code, ids, tau, *, mode, t, seed, rho, dtau, alpha, beta, tour=None):
                     p = tv
                     for _ in range(alpha - 1):
                         p = F32(p * tv)
-                ws.append(F32(p * _weight(2 if r in (2, 3) else 5, beta)))
-            s = F32(F32(F32(ws[0] + ws[1]) + ws[2]) + ws[3])
+                ws.append(F32(p * _weight(D2[r], beta)))
+            s = ws[0]
+            for wv in ws[1:]:
+                s = F32(s + wv)
             if s == F32(0.0):
                 req[y, x] = lem(avail, w[1], w[2])
                 continue
@@ -115,7 +123,7 @@ def step(code, ids, tau, *, mode, t, seed, rho, dtau, alpha, beta, tour=None):
             run = F32(0.0)
             pick = None
             last = None
-            for i, r in enumerate((2, 3, 4, 5)):
+            for i, r in enumerate(sides):
                 run = F32(run + ws[i])
                 if ws[i] > 0:
                     last = r

@@ -55,6 +55,7 @@ class Scenario:
     alpha: int = 1
     beta: int = 2
     tour: Optional[np.ndarray] = None  # float32 [N] initial tour lengths (tour variant), None = zeros
+    neighbours: int = 5  # 5: F, FD+-, L+- (no backward cells); 8: all eight neighbours
 
     @property
     def cross_a(self) -> int:
@@ -143,8 +144,8 @@ def make_scenario(W: int, H: int, n_a: int, n_b: int, *, band_a: int,
                   band_b: Optional[int] = None, seed: int = 1,
                   mode: int = MODE_ACO, steps: int = 0, obstacle_frac: float = 0.0,
                   tau0: float = 1.0, rho: float = 0.1, dtau: float = 1.0,
-                  alpha: int = 1, beta: int = 2, with_tau: Optional[bool] = None
-                  ) -> Scenario:
+                  alpha: int = 1, beta: int = 2, with_tau: Optional[bool] = None,
+                  neighbours: int = 5) -> Scenario:
     """Build one seeded scenario; `seed` drives placement and is also the
     step's RNG key."""
     if band_b is None:
@@ -159,7 +160,7 @@ def make_scenario(W: int, H: int, n_a: int, n_b: int, *, band_a: int,
     tau = np.full((2, H, W), np.float32(tau0), dtype=np.float32) if with_tau else None
     return Scenario(W=W, H=H, code=code, ids=ids, tau=tau, seed=seed, band_a=b_a,
                     band_b=b_b, n_a=n_a, n_b=n_b, mode=mode, steps=steps, tau0=tau0,
-                    rho=rho, dtau=dtau, alpha=alpha, beta=beta)
+                    rho=rho, dtau=dtau, alpha=alpha, beta=beta, neighbours=neighbours)
 
 
 def from_grid(code: np.ndarray, *, seed: int = 1, band_a: int = 1, band_b: int = 1,
@@ -207,7 +208,7 @@ def stress_4096x2048(mode: int = MODE_ACO, seed: int = 1) -> Scenario:
 
 
 def paper_sweep(densities=range(1, 21), repeats: int = 10, steps: int = 25000,
-                modes=(MODE_LEM, MODE_ACO), size: int = 480) -> List[Scenario]:
+                modes=(MODE_LEM, MODE_ACO), size: int = 480, neighbours: int = 5) -> List[Scenario]:
     """The population sweep of the paper's results (Sec. VI): a size x size
     grid, 1,280 k agents per group for density k (2,560 k in all), each group
     packed into the narrowest band that holds it (3 columns for k = 1), a
@@ -220,7 +221,7 @@ def paper_sweep(densities=range(1, 21), repeats: int = 10, steps: int = 25000,
         for rep in range(repeats):
             for mode in modes:
                 out.append(make_scenario(size, size, 1280 * k, 1280 * k, band_a=1, seed=100 * k + rep,
-                                         mode=mode, steps=steps))
+                                         mode=mode, steps=steps, neighbours=neighbours))
     return out
 
 

@@ -22,7 +22,8 @@ MUTANTS = {
                                "(r2 & 0u) ? plus_first : minus_first"),
     "lem_threshold_index_dropped": ("if (r1 >= lem_threshold[i]) index += 1;",
                                     "if (r1 >= lem_threshold[0]) index += 1;"),
-    "aco_weights_swapped": ("(i < 2 ? eta_diag : eta_lat)", "(i < 2 ? eta_lat : eta_diag)"),
+    "aco_weights_swapped": ("eta[0] = eta[1] = heuristic_weight(D2_DIAGONAL, p->beta);",
+                            "eta[0] = eta[1] = heuristic_weight(D2_LATERAL, p->beta);"),
     "aco_uses_r2": ("u = (float)(r1 >> 8) * 0x1p-24f;", "u = (float)(r2 >> 8) * 0x1p-24f;"),
     "aco_alpha_ignored": ("for (a = 1; a < alpha; ++a)", "for (a = 1; a < 1; ++a)"),
     "deposit_before_evaporation": ("float va = keep * tau_a[c];",
@@ -46,6 +47,13 @@ MUTANTS = {
         "if (entered[c] == O_B) evaporated_b = evaporated_b + p->dtau / tour[id[c] - 1u];",
         "if (entered[c] == O_B) evaporated_a = evaporated_a + p->dtau / tour[id[c] - 1u];"),
     "tour_group_of_target_not_mover": ("entered[c] = code[n];", "entered[c] = code[c];"),
+    "nb8_backward_is_forward": ("case O_REQ_B: *tx = x - d; break;", "case O_REQ_B: *tx = x + d; break;"),
+    "nb8_back_diagonal_sign": ("case O_REQ_BDP: *tx = x - d; *ty = y + 1; break;",
+                               "case O_REQ_BDP: *tx = x - d; *ty = y - 1; break;"),
+    "nb8_back_weights_swapped": ("eta[4] = heuristic_weight(D2_BACKWARD, p->beta);",
+                                 "eta[4] = heuristic_weight(D2_BACK_DIAGONAL, p->beta);"),
+    "nb8_back_pair_order_fixed": ("O_REQ_B, O_REQ_BDP, O_REQ_BDM};", "O_REQ_B, O_REQ_BDM, O_REQ_BDP};"),
+    "nb8_three_thresholds_only": ("for (i = 0; i < sides - 1; ++i)", "for (i = 0; i < 3; ++i)"),
 }
 
 

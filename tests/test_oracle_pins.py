@@ -107,7 +107,7 @@ def test_lem_thresholds_high_precision():
     mpmath = pytest.importorskip("mpmath")
     mpmath.mp.dps = 60
     want = []
-    for j in range(3):
+    for j in range(6):
         v = mpmath.ncdf(mpmath.mpf(j) + mpmath.mpf(1) / 2) * mpmath.mpf(2) ** 32
         assert abs(v - mpmath.nint(v)) > 1e-3  # not near an integer: ceil is robust
         want.append(int(mpmath.ceil(v)))
@@ -154,7 +154,7 @@ def test_heuristic_weights_correctly_rounded(beta):
     mpmath = pytest.importorskip("mpmath")
     mpmath.mp.dps = 60
     got = oracle.heuristic_weights(beta)
-    for d2, g in zip((1, 2, 5), got):
+    for d2, g in zip((1, 2, 5, 9, 10), got):
         exact = mpmath.power(mpmath.mpf(d2), -mpmath.mpf(beta) / 2)
         # nearest float32: compare against its two neighbours
         gf = mpmath.mpf(float(g))
@@ -268,7 +268,8 @@ def test_lone_agent_crosses_in_w_minus_1_steps(mode, group):
 # Invariants on seeded crowds
 # ----------------------------------------------------------------------------
 
-CAND = {1: (1, 0), 2: (1, -1), 3: (1, 1), 4: (0, -1), 5: (0, 1)}
+CAND = {1: (1, 0), 2: (1, -1), 3: (1, 1), 4: (0, -1), 5: (0, 1), 6: (-1, 0), 7: (-1, -1),
+        8: (-1, 1)}
 
 
 def _positions(code, ids):
@@ -276,7 +277,7 @@ def _positions(code, ids):
     return {int(ids[y, x]): (int(x), int(y), int(code[y, x])) for y, x in zip(ys, xs)}
 
 
-def check_step_invariants(code0, ids0, code1, ids1, req, moved, tau1=None):
+def check_step_invariants(code0, ids0, code1, ids1, req, moved, tau1=None, neighbours=5):
     H, W = code0.shape
     # walls never change, codes in range, ids consistent with codes
     assert np.array_equal(code0 == S.WALL, code1 == S.WALL)
@@ -293,6 +294,7 @@ def check_step_invariants(code0, ids0, code1, ids1, req, moved, tau1=None):
         r = int(req[y, x])
         d = 1 if g == S.GROUP_A else -1
         if r:
+            assert r <= (8 if neighbours == 8 else 5)
             ox, oy = CAND[r]
             tx, ty = x + ox * d, y + oy
             assert 0 <= tx < W and 0 <= ty < H and code0[ty, tx] == S.EMPTY
@@ -302,7 +304,7 @@ def check_step_invariants(code0, ids0, code1, ids1, req, moved, tau1=None):
         if (x1, y1) != (x, y):
             n_moved += 1
             assert r != 0 and (x1, y1) == (tx, ty)  # moved exactly to its request
-            assert (x1 - x) * d >= 0  # never backward
+            assert neighbours == 8 or (x1 - x) * d >= 0  # backward only with eight neighbours
     assert n_moved == moved
     # every requested cell received exactly one of its requesters
     for (tx, ty), ks in requested.items():
@@ -313,21 +315,23 @@ def check_step_invariants(code0, ids0, code1, ids1, req, moved, tau1=None):
         assert np.all(np.isfinite(tau1)) and np.all(tau1 >= 0)
 
 
+@pytest.mark.parametrize("neighbours", [5, 8])
 @pytest.mark.parametrize("mode", [oracle.MODE_LEM, oracle.MODE_ACO, oracle.MODE_ACO_TOUR])
 @pytest.mark.parametrize("seed,obst", [(3, 0.0), (4, 0.08)])
-def test_invariants_every_step(mode, seed, obst):
+def test_invariants_every_step(mode, seed, obst, neighbours):
     s = S.make_scenario(64, 32, 260, 240, band_a=6, seed=seed, mode=mode,
-                        obstacle_frac=obst, with_tau=True)
+                        obstacle_frac=obst, with_tau=True, neighbours=neighbours)
     st = oracle.State.from_scenario(s)
     last = st.counts()
     for _ in range(70):
         c0, i0 = st.code.copy(), st.ids.copy()
         moved, req, win = st.step(mode, want_detail=True)
         check_step_invariants(c0, i0, st.code, st.ids, req, moved,
-                              st.tau if mode != oracle.MODE_LEM else None)
+                              st.tau if mode != oracle.MODE_LEM else None, neighbours)
         now = st.counts()
         assert now[0] == last[0] and now[1] == last[1]
-        assert now[2] >= last[2] and now[3] >= last[3]  # crossings are monotone
+        if neighbours == 5:
+            assert now[2] >= last[2] and now[3] >= last[3]  # crossings are monotone
         last = now
 
 
@@ -364,15 +368,16 @@ def mosaic(grids, per_row=128):
     return code, origins
 
 
-def test_bruteforce_4x4_resolution_is_the_lowest_ticket_outcome():
+@pytest.mark.parametrize("neighbours", [5, 8])
+def test_bruteforce_4x4_resolution_is_the_lowest_ticket_outcome(neighbours):
     grids = all_small_grids(4, 4)
     assert len(grids) == 1 + 32 + 480 + 4480 + 29120
     code, origins = mosaic(grids)
-    s = S.from_grid(code, seed=2024)
+    s = S.from_grid(code, seed=2024, neighbours=neighbours)
     st = oracle.State.from_scenario(s)
     c0, i0 = st.code.copy(), st.ids.copy()
     moved, req, win = st.step(oracle.MODE_LEM, want_detail=True)
-    check_step_invariants(c0, i0, st.code, st.ids, req, moved)
+    check_step_invariants(c0, i0, st.code, st.ids, req, moved, neighbours=neighbours)
     # referee: for every requested cell, enumerate its requesters; the valid
     # outcomes are one requester per cell; the oracle must pick the one with
     # the lowest (ticket, k) at every cell and leave every other agent home.
@@ -516,18 +521,21 @@ def test_conflict_winner_uniform_over_requesters():
 # Two independent implementations agree
 # ----------------------------------------------------------------------------
 
-@pytest.mark.parametrize("mode,alpha,beta,seed", [
-    (oracle.MODE_LEM, 1, 2, 1), (oracle.MODE_ACO, 1, 2, 2), (oracle.MODE_ACO, 2, 3, 3),
-    (oracle.MODE_ACO, 0, 1, 4)])
-def test_python_reference_agrees_bit_for_bit(mode, alpha, beta, seed):
+@pytest.mark.parametrize("mode,alpha,beta,seed,neighbours", [
+    (oracle.MODE_LEM, 1, 2, 1, 5), (oracle.MODE_ACO, 1, 2, 2, 5), (oracle.MODE_ACO, 2, 3, 3, 5),
+    (oracle.MODE_ACO, 0, 1, 4, 5), (oracle.MODE_LEM, 1, 2, 5, 8), (oracle.MODE_ACO, 1, 2, 6, 8),
+    (oracle.MODE_ACO, 2, 3, 7, 8)])
+def test_python_reference_agrees_bit_for_bit(mode, alpha, beta, seed, neighbours):
     s = S.make_scenario(26, 12, 45, 40, band_a=4, seed=seed, mode=mode, obstacle_frac=0.06,
-                        with_tau=True, alpha=alpha, beta=beta, rho=0.05, dtau=0.5)
+                        with_tau=True, alpha=alpha, beta=beta, rho=0.05, dtau=0.5,
+                        neighbours=neighbours)
     st = oracle.State.from_scenario(s)
     code, ids, tau = s.code.copy(), s.ids.copy(), s.tau.copy()
     for t in range(30):
         moved = st.step(mode)
         code, ids, tau, req, m2 = ref.step(code, ids, tau, mode=mode, t=t, seed=seed,
-                                           rho=0.05, dtau=0.5, alpha=alpha, beta=beta)
+                                           rho=0.05, dtau=0.5, alpha=alpha, beta=beta,
+                                           neighbours=neighbours)
         assert moved == m2
         assert np.array_equal(code, st.code) and np.array_equal(ids, st.ids)
         assert np.array_equal(tau.view(np.uint32), st.tau.view(np.uint32))
@@ -642,11 +650,12 @@ def test_tour_lengths_and_deposits_follow_displacements(seed, obst, initial):
     assert np.all(err <= (moves + 2) * 2.0 ** -23 * np.maximum(length, 1.0))
 
 
-@pytest.mark.parametrize("alpha,beta,seed,initial", [(1, 2, 8, False), (2, 1, 9, True)])
-def test_tour_python_reference_agrees_bit_for_bit(alpha, beta, seed, initial):
+@pytest.mark.parametrize("alpha,beta,seed,initial,neighbours", [
+    (1, 2, 8, False, 5), (2, 1, 9, True, 5), (1, 2, 10, True, 8)])
+def test_tour_python_reference_agrees_bit_for_bit(alpha, beta, seed, initial, neighbours):
     s = S.make_scenario(26, 12, 45, 40, band_a=4, seed=seed, mode=S.MODE_ACO_TOUR,
                         obstacle_frac=0.06, with_tau=True, alpha=alpha, beta=beta,
-                        rho=0.05, dtau=0.5)
+                        rho=0.05, dtau=0.5, neighbours=neighbours)
     if initial:
         s.tour = (np.random.default_rng(seed).random(s.agents) * 9).astype(np.float32)
     st = oracle.State.from_scenario(s)
@@ -656,8 +665,109 @@ def test_tour_python_reference_agrees_bit_for_bit(alpha, beta, seed, initial):
         moved = st.step(oracle.MODE_ACO_TOUR)
         code, ids, tau, tour, req, m2 = ref.step(code, ids, tau, mode=2, t=t, seed=seed,
                                                  rho=0.05, dtau=0.5, alpha=alpha, beta=beta,
-                                                 tour=tour)
+                                                 tour=tour, neighbours=neighbours)
         assert moved == m2
         assert np.array_equal(code, st.code) and np.array_equal(ids, st.ids)
         assert np.array_equal(tau.view(np.uint32), st.tau.view(np.uint32))
         assert np.array_equal(tour.view(np.uint32), st.tour.view(np.uint32))
+
+
+# ----------------------------------------------------------------------------
+# Eight neighbours: backward cells ranked last (Sec. III, Sec. IV.b-c)
+# ----------------------------------------------------------------------------
+
+def _open_pockets(n, walls=(), tau_values=None):
+    """n copies of a lone A agent in the middle of a 3x3 block whose forward
+    cell is a wall; `walls` lists further (dx, dy) offsets to wall off."""
+    per_row = 150
+    rows = (n + per_row - 1) // per_row
+    H, W = rows * 4 + 1, per_row * 4 + 1
+    code = np.full((H, W), S.WALL, np.uint8)
+    tau = np.ones((2, H, W), np.float32)
+    agents = []
+    for i in range(n):
+        oy, ox = 1 + (i // per_row) * 4, 1 + (i % per_row) * 4
+        code[oy:oy + 3, ox:ox + 3] = S.EMPTY
+        cx, cy = ox + 1, oy + 1
+        code[cy, cx] = S.GROUP_A
+        code[cy, cx + 1] = S.WALL
+        for (dx, dy) in walls:
+            code[cy + dy, cx + dx] = S.WALL
+        if tau_values is not None:
+            for (dx, dy), v in tau_values.items():
+                tau[0, cy + dy, cx + dx] = v
+        agents.append((cx, cy))
+    return code, tau, agents
+
+
+def test_nb8_lem_ranks_seven_candidates():
+    """All seven side candidates empty: the rank index follows the normal
+    thresholds over [FD_s, FD_-s, L_s, L_-s, B, BD_s, BD_-s]."""
+    from scipy.stats import chisquare
+    from oracle.ref import _phi
+    code, tau, agents = _open_pockets(45000)
+    st = oracle.State.from_scenario(S.from_grid(code, seed=77, neighbours=8))
+    ids0 = st.ids.copy()
+    _, req, _ = st.step(oracle.MODE_LEM, want_detail=True)
+    counts = np.zeros(7)
+    for (x, y) in agents:
+        k = int(ids0[y, x]) - 1
+        r2 = ref.philox4x32_10((k, 0, 0, 0), (77, 0))[2]
+        order = [3, 2, 5, 4, 6, 8, 7] if (r2 & 1) else [2, 3, 4, 5, 6, 7, 8]
+        counts[order.index(int(req[y, x]))] += 1
+    p = [_phi(0.5)] + [_phi(j + 0.5) - _phi(j - 0.5) for j in range(1, 4)] + [1 - _phi(3.5)]
+    obs = list(counts[:4]) + [counts[4:].sum()]
+    assert chisquare(obs, np.array(p) * counts.sum()).pvalue > 1e-4
+    assert counts[4] > 0  # the backward cell is reachable
+
+
+def test_nb8_backward_only_candidates():
+    """Forward, diagonals and laterals walled: B first, then the backward
+    diagonals in the side-bit order, index clamped at 2."""
+    from scipy.stats import chisquare
+    from oracle.ref import _phi
+    walls = ((1, -1), (1, 1), (0, -1), (0, 1))
+    code, tau, agents = _open_pockets(30000, walls)
+    st = oracle.State.from_scenario(S.from_grid(code, seed=78, neighbours=8))
+    ids0 = st.ids.copy()
+    _, req, _ = st.step(oracle.MODE_LEM, want_detail=True)
+    counts = np.zeros(3)
+    for (x, y) in agents:
+        k = int(ids0[y, x]) - 1
+        r2 = ref.philox4x32_10((k, 0, 0, 0), (78, 0))[2]
+        order = [6, 8, 7] if (r2 & 1) else [6, 7, 8]
+        counts[order.index(int(req[y, x]))] += 1
+    p = np.array([_phi(0.5), _phi(1.5) - _phi(0.5), 1 - _phi(1.5)])
+    assert chisquare(counts, p * counts.sum()).pvalue > 1e-4
+    # every agent moved backward: nothing else was open
+    assert np.all(st.code[[y for (_, y) in agents], [x for (x, _) in agents]] == S.EMPTY)
+
+
+def test_nb8_aco_weights_include_backward_cells():
+    from scipy.stats import chisquare
+    taus = {(1, -1): 1.0, (1, 1): 2.0, (0, -1): 3.0, (0, 1): 1.0, (-1, 0): 9.0,
+            (-1, -1): 5.0, (-1, 1): 10.0}
+    code, tau, agents = _open_pockets(45000, (), taus)
+    st = oracle.State.from_scenario(S.from_grid(code, seed=79, tau=tau, neighbours=8))
+    _, req, _ = st.step(oracle.MODE_ACO, want_detail=True)
+    r = np.array([req[y, x] for (x, y) in agents])
+    # tau * eta^2 with eta^2 = 1/2 (FD), 1/5 (L), 1/9 (B), 1/10 (BD)
+    w = np.array([1 / 2, 2 / 2, 3 / 5, 1 / 5, 9 / 9, 5 / 10, 10 / 10])
+    counts = np.array([np.sum(r == c) for c in range(2, 9)])
+    assert chisquare(counts, w / w.sum() * counts.sum()).pvalue > 1e-4
+
+
+def test_nb8_lone_agent_steps_back_at_the_far_end():
+    """In a one-row corridor the agent walks to the far column in W-1 steps;
+    there its only open candidate is the cell behind it, and from there the
+    forward cell is open again: it alternates between the last two columns."""
+    W, H = 9, 3
+    code = S.wall_frame(W, H)
+    code[1, 0] = S.GROUP_A
+    st = oracle.State.from_scenario(S.from_grid(code, neighbours=8))
+    for _ in range(W - 1):
+        st.step(oracle.MODE_LEM)
+    assert st.code[1, W - 1] == S.GROUP_A
+    for t in range(6):
+        st.step(oracle.MODE_LEM)
+        assert st.code[1, W - 2 if t % 2 == 0 else W - 1] == S.GROUP_A
