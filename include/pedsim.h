@@ -144,6 +144,21 @@ int sim_attach_tour(sim_handle* h, float* d_tour, float* d_tour_shadow, void* st
  */
 int sim_step_aco_tour(sim_handle* h, int32_t nsteps, void* stream);
 
+/*
+ * Candidate set of every later step on h: n = 5 (F, FD-, FD+, L-, L+; the
+ * default) or n = 8, the paper's full neighbourhood (Sec. III) with the
+ * backward cells B (x-d, y), BD- (x-d, y-1) and BD+ (x-d, y+1) ranked after
+ * the laterals (Sec. IV.b-c): squared distances 9 and 10 to the point two
+ * cells ahead give their heuristic weights, the LEM rank order is
+ * [FD_s, FD_-s, L_s, L_-s, B, BD_s, BD_-s] with six normal thresholds, and
+ * the ACO roulette sums seven weights in the order FD-, FD+, L-, L+, B, BD-,
+ * BD+. A tour-variant move to a backward diagonal adds fl(sqrt 2), to B 1.
+ * With n = 8 every mode runs on the row-lane engine with the pheromone in
+ * LDS (nw = 0). Resets every mode's tiling to that set's default. SIM_EINVAL
+ * for other n. Not available in batches.
+ */
+int sim_set_neighbours(sim_handle* h, int32_t n);
+
 /* Counters after the last completed step; synchronises `stream`. */
 int sim_stats(sim_handle* h, sim_stats_t* out, void* stream);
 

@@ -73,6 +73,9 @@ Scenario base_scenario(const sim_params* p) {
   S.eta_diag = heuristic(2.0, p->beta);
   S.eta_lat = heuristic(5.0, p->beta);
   S.step_diag = sqrtf(2.0f);
+  S.eta_back = heuristic(9.0, p->beta);
+  S.eta_back_diag = heuristic(10.0, p->beta);
+  S.neighbours = 5;
   S.alpha = p->alpha;
   S.cross_a = p->cross_a;
   S.cross_b = p->cross_b;
@@ -128,7 +131,7 @@ namespace {
 // (its deposits depend on per-move tour lengths, so they are applied in LDS
 // as they happen); its extra per-cell tour lengths make the 56-row shape too
 // big for two workgroups per compute unit, so medium grids use 48 rows.
-Tiling default_tiling(int mode, size_t cells) {
+Tiling default_tiling(int mode, size_t cells, bool nb8 = false) {
   static const Tiling tiny_opts[] = {{0, 48, 6, 512}, {0, 32, 4, 256}, {1, 32, 1, 256}};
   static const Tiling small_opts[] = {{0, 56, 4, 512}, {0, 48, 3, 512}, {1, 32, 1, 256}};
   static const Tiling large_opts[] = {{3, 48, 2, 256}, {0, 48, 2, 512}, {1, 32, 1, 256}};
@@ -138,9 +141,9 @@ Tiling default_tiling(int mode, size_t cells) {
   const int size = cells < ((size_t)1 << 18) ? 0 : (cells < ((size_t)2 << 20) ? 1 : 2);
   const Tiling* const plain[3] = {tiny_opts, small_opts, large_opts};
   const Tiling* const tour[3] = {tour_tiny, tour_small, tour_large};
-  const Tiling* opts = mode == kModeAcoTour ? tour[size] : plain[size];
+  const Tiling* opts = (mode == kModeAcoTour || nb8) ? tour[size] : plain[size];
   for (int i = 0; i < 3; ++i)
-    if (tiling_valid(opts[i], mode, max_dynamic_lds())) return opts[i];
+    if (tiling_valid(opts[i], mode, max_dynamic_lds(), nb8)) return opts[i];
   return opts[2];
 }
 
@@ -361,11 +364,19 @@ int sim_attach_tour(sim_handle* h, float* d_tour, float* d_tour_shadow, void* st
   return SIM_OK;
 }
 
+int sim_set_neighbours(sim_handle* h, int32_t n) {
+  if (!h || (n != 5 && n != 8)) return SIM_EINVAL;
+  h->base.neighbours = n;
+  const size_t cells = (size_t)h->p.W * (size_t)h->p.H;
+  for (int m = 0; m < 3; ++m) h->tiling[m] = default_tiling(m, cells, n == 8);
+  return SIM_OK;
+}
+
 int sim_set_tiling(sim_handle* h, int32_t mode, int32_t nw, int32_t rows, int32_t steps_per_launch,
                    int32_t threads) {
   if (!h || (mode != kModeLem && mode != kModeAco && mode != kModeAcoTour)) return SIM_EINVAL;
   const Tiling tl{nw, rows, steps_per_launch, threads};
-  if (!tiling_valid(tl, mode, max_dynamic_lds())) return SIM_EINVAL;
+  if (!tiling_valid(tl, mode, max_dynamic_lds(), h->base.neighbours == 8)) return SIM_EINVAL;
   Scenario S = h->base;
   set_geometry(S, tl);
   if (S.tiles_x * S.tiles_y > h->stats_cap) return SIM_EINVAL;

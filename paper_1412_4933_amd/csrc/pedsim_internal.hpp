@@ -34,11 +34,12 @@ constexpr int kMinInteriorY = 8;
 inline bool rows_engine(const Tiling& tl) { return tl.nw == 0 || tl.nw == 3; }
 inline bool rows_stream(const Tiling& tl) { return tl.nw == 3; }
 inline int region_cols(const Tiling& tl) { return rows_engine(tl) ? 64 : 64 * tl.nw; }
-// LDS of one workgroup for `mode`; a tiling is valid for a mode when its
-// shape is allowed, fits max_lds, and (tour variant) uses the row-lane engine
-// with the pheromone staged in LDS (nw = 0).
-size_t tile_lds_bytes(const Tiling& tl, int mode);
-bool tiling_valid(const Tiling& tl, int mode, int max_lds);
+// LDS of one workgroup for `mode` (nb8: the eight-neighbour candidate set);
+// a tiling is valid for a mode when its shape is allowed, fits max_lds, and
+// (tour variant, eight neighbours) uses the row-lane engine with the
+// pheromone staged in LDS (nw = 0).
+size_t tile_lds_bytes(const Tiling& tl, int mode, bool nb8 = false);
+bool tiling_valid(const Tiling& tl, int mode, int max_lds, bool nb8 = false);
 
 // One launch of the tile engine over every tile of S.
 hipError_t launch_tiles(const Scenario& S, const Tiling& tl, int mode, uint64_t t0, int steps, int last,

@@ -121,4 +121,70 @@ __device__ __forceinline__ int aco_choose(unsigned avail, const float tau[4], in
   return kReqFDm + (pick >= 0 ? pick : last);
 }
 
+// Eight-neighbour candidate set (Sec. III): side candidates numbered
+// j = 0 FD- (x+d, y-1), 1 FD+ (x+d, y+1), 2 L- (x, y-1), 3 L+ (x, y+1),
+// 4 B (x-d, y), 5 BD- (x-d, y-1), 6 BD+ (x-d, y+1); the backward cells are
+// ranked after the laterals (Sec. IV.b-c). Thresholds T_3..T_5 continue the
+// ones above (Phi(3.5) = 0.999767370..., Phi(4.5) = 0.999996602...,
+// Phi(5.5) = 0.999999981...).
+constexpr uint32_t kNormalCut3 = 4293968162u;
+constexpr uint32_t kNormalCut4 = 4294952704u;
+constexpr uint32_t kNormalCut5 = 4294967215u;
+
+// LEM over the seven side candidates: ranks [FD_s, FD_-s, L_s, L_-s, B,
+// BD_s, BD_-s] (s from bit 0 of w2 as above). Returns the candidate j, or -1
+// when avail == 0.
+__device__ __forceinline__ int lem_choose7(unsigned avail, uint32_t w1, uint32_t w2) {
+  const unsigned flip = w2 & 1u;
+  const int n = __popc(avail);
+  int idx = (w1 >= kNormalCut0) + (w1 >= kNormalCut1) + (w1 >= kNormalCut2) + (w1 >= kNormalCut3) +
+            (w1 >= kNormalCut4) + (w1 >= kNormalCut5);
+  idx = idx < n - 1 ? idx : n - 1;
+  int pick = -1;
+#pragma unroll
+  for (int rank = 0; rank < 7; ++rank) {
+    const int j = rank < 4 ? (rank ^ (int)flip) : (rank == 4 ? 4 : 5 + ((rank - 5) ^ (int)flip));
+    if ((avail >> j) & 1u) {
+      if (idx == 0 && pick < 0) pick = j;
+      idx -= 1;
+    }
+  }
+  return pick;
+}
+
+// ACO over the seven side candidates: weights tau^alpha * eta^beta in the
+// order FD-, FD+, L-, L+, B, BD-, BD+ (eta[j] per candidate), summed left to
+// right, roulette as in aco_choose; all-zero weights fall back to
+// lem_choose7 with the same words. Returns the candidate j.
+__device__ __forceinline__ int aco_choose7(unsigned avail, const float tau[7], int alpha, const float eta[7],
+                                           uint32_t w1, uint32_t w2) {
+  float w[7];
+#pragma unroll
+  for (int j = 0; j < 7; ++j) {
+    float p = 1.0f;
+    if (alpha > 0) {
+      p = tau[j];
+      for (int a = 1; a < alpha; ++a) p = p * tau[j];
+    }
+    w[j] = ((avail >> j) & 1u) ? p * eta[j] : 0.0f;
+  }
+  float sum = w[0];
+#pragma unroll
+  for (int j = 1; j < 7; ++j) sum = sum + w[j];
+  if (sum == 0.0f) return lem_choose7(avail, w1, w2);
+  const float u = (float)(w1 >> 8) * 0x1p-24f;
+  const float target = u * sum;
+  float running = 0.0f;
+  int last = -1, pick = -1;
+#pragma unroll
+  for (int j = 0; j < 7; ++j) {
+    running = running + w[j];
+    if (w[j] > 0.0f) {
+      last = j;
+      if (pick < 0 && target < running) pick = j;
+    }
+  }
+  return pick >= 0 ? pick : last;
+}
+
 }  // namespace pedsim

@@ -21,32 +21,32 @@ __global__ __launch_bounds__(1024) void tile_kernel(Scenario S, int R, uint64_t 
   advance_tile<NW, MODE>(S, smem, R, tile % S.tiles_x, tile / S.tiles_x, tile, t0, steps, last != 0);
 }
 
-template <int MODE, bool STREAM>
+template <int MODE, bool STREAM, bool NB8 = false>
 __global__ __launch_bounds__(kRowsMaxThreads, kRowsMinWavesPerSimd) void tile_rows_kernel(Scenario S, int R, int k_max, uint64_t t0,
                                                                     int steps, int last) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int ntiles = S.tiles_x * S.tiles_y;
   const int tile = tile_of_block(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
-  advance_tile_rows<MODE, STREAM>(S, smem, R, k_max, tile % S.tiles_x, tile / S.tiles_x, tile, t0, steps,
-                                  last != 0);
+  advance_tile_rows<MODE, STREAM, NB8>(S, smem, R, k_max, tile % S.tiles_x, tile / S.tiles_x, tile, t0, steps,
+                                       last != 0);
 }
 
-size_t tile_lds_bytes(const Tiling& tl, int mode) {
+size_t tile_lds_bytes(const Tiling& tl, int mode, bool nb8) {
   const bool aco = mode != kModeLem;
-  if (rows_engine(tl)) return RowsLayout{tl.rows, tl.steps, aco, rows_stream(tl), mode == kModeAcoTour}.bytes();
+  if (rows_engine(tl)) return RowsLayout{tl.rows, tl.steps, aco, rows_stream(tl), mode == kModeAcoTour, nb8}.bytes();
   return tl.nw == 1 ? Layout<1>{tl.rows, aco}.bytes() : Layout<2>{tl.rows, aco}.bytes();
 }
 
-bool tiling_valid(const Tiling& tl, int mode, int max_lds) {
+bool tiling_valid(const Tiling& tl, int mode, int max_lds, bool nb8) {
   if (tl.nw < 0 || tl.nw > 3) return false;
-  if (mode == kModeAcoTour && tl.nw != 0) return false;
+  if ((mode == kModeAcoTour || nb8) && tl.nw != 0) return false;
   if (rows_engine(tl) && (tl.rows > kRowsMaxRows || tl.steps > kRowsMaxSteps || tl.threads > kRowsMaxThreads))
     return false;
   if (tl.steps < 1 || tl.threads < 64 || tl.threads > 1024 || tl.threads % 64) return false;
   if (tl.rows < 1 || tl.rows > 1023) return false;
   if (region_cols(tl) - 6 * tl.steps < kMinInteriorX || tl.rows - 6 * tl.steps < kMinInteriorY) return false;
-  return tile_lds_bytes(tl, mode) <= (size_t)max_lds;
+  return tile_lds_bytes(tl, mode, nb8) <= (size_t)max_lds;
 }
 
 int max_dynamic_lds() {
@@ -77,24 +77,30 @@ static hipError_t launch_one(const Scenario& S, const Tiling& tl, uint64_t t0, i
   return hipGetLastError();
 }
 
-template <int MODE, bool STREAM>
+template <int MODE, bool STREAM, bool NB8 = false>
 static hipError_t launch_rows(const Scenario& S, const Tiling& tl, uint64_t t0, int steps, int last, hipStream_t s) {
-  const size_t lds = RowsLayout{tl.rows, tl.steps, MODE != kModeLem, STREAM, MODE == kModeAcoTour}.bytes();
+  const size_t lds = RowsLayout{tl.rows, tl.steps, MODE != kModeLem, STREAM, MODE == kModeAcoTour, NB8}.bytes();
   static bool attr_done = false;
   if (!attr_done) {
-    (void)hipFuncSetAttribute((const void*)tile_rows_kernel<MODE, STREAM>,
+    (void)hipFuncSetAttribute((const void*)tile_rows_kernel<MODE, STREAM, NB8>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, max_dynamic_lds());
     (void)hipGetLastError();  // an unsupported attribute value must not linger as the last error
     attr_done = true;
   }
   const int ntiles = S.tiles_x * S.tiles_y;
   const int blocks = ((ntiles + 7) / 8) * 8;
-  tile_rows_kernel<MODE, STREAM><<<blocks, tl.threads, lds, s>>>(S, tl.rows, tl.steps, t0, steps, last);
+  tile_rows_kernel<MODE, STREAM, NB8><<<blocks, tl.threads, lds, s>>>(S, tl.rows, tl.steps, t0, steps, last);
   return hipGetLastError();
 }
 
 hipError_t launch_tiles(const Scenario& S, const Tiling& tl, int mode, uint64_t t0, int steps, int last,
                         hipStream_t s) {
+  if (S.neighbours == 8) {  // the eight-neighbour set: row-lane engine, pheromone in LDS
+    if (tl.nw != 0) return hipErrorInvalidValue;
+    if (mode == kModeLem) return launch_rows<kModeLem, false, true>(S, tl, t0, steps, last, s);
+    if (mode == kModeAco) return launch_rows<kModeAco, false, true>(S, tl, t0, steps, last, s);
+    return launch_rows<kModeAcoTour, false, true>(S, tl, t0, steps, last, s);
+  }
   if (mode == kModeAcoTour) {
     if (tl.nw != 0) return hipErrorInvalidValue;
     return launch_rows<kModeAcoTour, false>(S, tl, t0, steps, last, s);

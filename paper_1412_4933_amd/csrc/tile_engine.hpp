@@ -88,6 +88,8 @@ struct Scenario {
   uint32_t key0, key1;
   float keep, dtau, eta_diag, eta_lat;
   float step_diag;  // tour variant: length of a diagonal move, fl(sqrt 2)
+  float eta_back, eta_back_diag;  // eight neighbours: eta^beta of B (D2 = 9) and BD (D2 = 10)
+  int neighbours;                 // 5 (no backward cells) or 8
   int alpha;
   int cross_a, cross_b;
 };

@@ -63,10 +63,11 @@ struct RowsLayout {
   bool aco;
   bool stream;        // pheromone read from HBM, tickets recomputed: no tick or tau arrays
   bool tour = false;  // tour variant: tour lengths per cell
+  bool nb8 = false;   // eight-neighbour candidates: side requests kept per move direction (8 masks)
   __host__ __device__ size_t hist() const { return 0; }                                  // [k+1][2][R] u64
   __host__ __device__ size_t wall() const { return hist() + (size_t)(k + 1) * 2 * R * 8; }  // [R] u64
   __host__ __device__ size_t side() const { return wall() + (size_t)R * 8; }             // [6][R] u64
-  __host__ __device__ size_t reqm() const { return side() + (size_t)6 * R * 8; }         // [8][R] u64
+  __host__ __device__ size_t reqm() const { return side() + (size_t)(nb8 ? 8 : 6) * R * 8; }  // [8][R] u64
   __host__ __device__ size_t cwin() const { return reqm() + (size_t)8 * R * 8; }         // [8][R] u64
   __host__ __device__ size_t moved() const { return cwin() + (size_t)8 * R * 8; }        // [R] u64
   __host__ __device__ size_t ctl() const { return moved() + (size_t)R * 8; }             // 16 u32
@@ -151,10 +152,17 @@ __device__ __forceinline__ void stage_issue(const Scenario& S, int R, int x0, in
 // contest tickets are recomputed instead of kept per cell, which leaves ids,
 // masks and the queue as the region's only LDS and lets more workgroups share
 // a compute unit on large grids.
-template <int MODE, bool STREAM = false>
+// NB8: the paper's full neighbourhood (Sec. III), backward cells ranked last.
+// Side requests are then kept by move direction rather than by kind and
+// group: direction q moves an agent from the neighbour at (dir_dc(q),
+// dir_dr(q)) of a cell into the cell, i.e. by the vector (-dir_dc(q),
+// -dir_dr(q)); forward moves are directions 0 (A) and 1 (B), and every
+// direction may carry either group.
+template <int MODE, bool STREAM = false, bool NB8 = false>
 __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k_max, int tx, int ty, int tile_index,
                                   uint64_t t0, int steps, bool last) {
-  const RowsLayout L{R, k_max, MODE != 0, STREAM, MODE == 2};
+  static_assert(!(NB8 && STREAM), "the eight-neighbour set runs on the LDS form only");
+  const RowsLayout L{R, k_max, MODE != 0, STREAM, MODE == 2, NB8};
   uint64_t* hist = (uint64_t*)(smem + L.hist());
   uint64_t* wall_m = (uint64_t*)(smem + L.wall());
   uint64_t* side = (uint64_t*)(smem + L.side());
@@ -231,14 +239,64 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
   }
   uint64_t moved_in = 0ull;
   uint64_t fA = 0ull, fB = 0ull;
-  uint64_t rq[6] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+  uint64_t rq[8];  // single-candidate side requests (six kinds, or eight move directions with NB8)
+#pragma unroll
+  for (int q = 0; q < 8; ++q) rq[q] = 0ull;
   uint64_t Wt[8];
 
   for (int s = 0; s < steps; ++s) {
     const uint64_t t = t0 + (uint64_t)s;
 
     // ---- 1. masks: requests that need no random word; who must draw -------
-    if (mask_wave) {
+    if (NB8 && mask_wave) {
+      const uint64_t E = ~(A | B | Wl);
+      const uint64_t Eu = from_up(E), Ed = from_down(E);
+      const uint64_t e_r = E >> 1, e_l = E << 1;  // cell to the right / left is empty
+      fA = A & e_r;
+      fB = B & e_l;
+      const uint64_t bl = (A & ~e_r) | (B & ~e_l);  // agents whose forward cell is blocked
+      // their empty side candidates by move vector (dx, dy) of direction q
+      uint64_t Sq[8];
+      Sq[0] = B & ~e_l & e_r;  // (+1, 0): B backward
+      Sq[1] = A & ~e_r & e_l;  // (-1, 0): A backward
+      Sq[2] = bl & (Eu >> 1);  // (+1, -1)
+      Sq[3] = bl & (Ed >> 1);  // (+1, +1)
+      Sq[4] = bl & (Eu << 1);  // (-1, -1)
+      Sq[5] = bl & (Ed << 1);  // (-1, +1)
+      Sq[6] = bl & Eu;         // (0, -1)
+      Sq[7] = bl & Ed;         // (0, +1)
+      uint64_t ones = 0ull, multi = 0ull;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        multi |= ones & Sq[q];
+        ones |= Sq[q];
+      }
+      const uint64_t single = ones & ~multi;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) rq[q] = single & Sq[q];
+      // possible requesters of each cell, by direction; two or more: contestable
+      const uint64_t Pv0 = Sq[0] | fA, Pv1 = Sq[1] | fB;
+      const uint64_t P[8] = {Pv0 << 1,           Pv1 >> 1,           from_down(Sq[2]) << 1, from_up(Sq[3]) << 1,
+                             from_down(Sq[4]) >> 1, from_up(Sq[5]) >> 1, from_down(Sq[6]),       from_up(Sq[7])};
+      uint64_t pones = 0ull, twos = 0ull;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        twos |= pones & P[q];
+        pones |= P[q];
+      }
+      const uint64_t pu = from_up(twos), pd = from_down(twos);
+      const uint64_t need = (Pv0 & (twos >> 1)) | (Pv1 & (twos << 1)) | (Sq[2] & (pu >> 1)) | (Sq[3] & (pd >> 1)) |
+                            (Sq[4] & (pu << 1)) | (Sq[5] & (pd << 1)) | (Sq[6] & pu) | (Sq[7] & pd);
+      if (row_lane) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) side[q * R + lane] = 0ull;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cwin[q * R + lane] = 0ull;
+      }
+      const int nq = enqueue_row_bits(queue, multi | need, lane);
+      if (lane == 0) ctl[0] = (uint32_t)nq;
+    }
+    if (!NB8 && mask_wave) {
       const uint64_t E = ~(A | B | Wl);
       const uint64_t Eu = from_up(E), Ed = from_down(E);
       const uint64_t e_r = E >> 1, e_l = E << 1;  // cell to the right / left is empty
@@ -312,7 +370,67 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
                                (((unsigned)(eu >> c) & 1u) << 2) | (((unsigned)(ed >> c) & 1u) << 3);
         const Words w = agent_words(id - 1u, t, S.key0, S.key1);
         if (!STREAM) tick[r * 64 + c] = w.w0;
-        if (!fwd && (avail & (avail - 1u)) != 0u) {  // two or more side candidates: a choice
+        if constexpr (NB8) {
+          // backward column; candidates 4 B (r, cbc), 5 BD- (ru, cbc), 6 BD+ (rd, cbc)
+          const int cb = c - d;
+          const bool cb_in = cb >= 0 && cb < 64;
+          const int cbc = cb_in ? cb : c;
+          const unsigned bk = cb_in ? 1u : 0u;
+          const unsigned avail7 = avail | ((bk & (unsigned)(e0 >> cbc)) << 4) | ((bk & (unsigned)(eu >> cbc)) << 5) |
+                                  ((bk & (unsigned)(ed >> cbc)) << 6);
+          if (!fwd && (avail7 & (avail7 - 1u)) != 0u) {  // two or more side candidates: a choice
+            int j;
+            if (MODE == 0) {
+              j = lem_choose7(avail7, w.w1, w.w2);
+            } else {
+              const int gp = is_a ? 0 : 1;
+              const float* tp = is_a ? tau_a : tau_b;
+              // candidate rows: 0 = ru, 1 = rd, 2 = r
+              const int rsel[7] = {0, 1, 0, 1, 2, 0, 1};
+              const int cc[7] = {cfc, cfc, c, c, cbc, cbc, cbc};
+              const int rows3[3] = {ru, rd, r};
+              float tau[7];
+#pragma unroll
+              for (int k = 0; k < 7; ++k) tau[k] = tp[rows3[rsel[k]] * 64 + cc[k]];
+              if (MODE == 1) {
+                for (int u = 1; u <= s; ++u) {
+                  const uint64_t hv[3] = {H(u, gp, ru), H(u, gp, rd), H(u, gp, r)};
+#pragma unroll
+                  for (int k = 0; k < 7; ++k) {
+                    tau[k] = S.keep * tau[k];
+                    if ((hv[rsel[k]] >> cc[k]) & 1ull) tau[k] = tau[k] + S.dtau;
+                  }
+                }
+              } else {  // the LDS value is current through the cell's last deposit
+                int owed[7];
+#pragma unroll
+                for (int k = 0; k < 7; ++k) owed[k] = s;
+                for (int u = 0; u < s; ++u) {
+                  const uint64_t nv[3] = {H(u + 1, gp, ru) & ~(H(u, 0, ru) | H(u, 1, ru)),
+                                          H(u + 1, gp, rd) & ~(H(u, 0, rd) | H(u, 1, rd)),
+                                          H(u + 1, gp, r) & ~(H(u, 0, r) | H(u, 1, r))};
+#pragma unroll
+                  for (int k = 0; k < 7; ++k)
+                    if ((nv[rsel[k]] >> cc[k]) & 1ull) owed[k] = s - 1 - u;
+                }
+                for (int u = 0; u < s; ++u) {
+#pragma unroll
+                  for (int k = 0; k < 7; ++k)
+                    if (u >= s - owed[k]) tau[k] = S.keep * tau[k];
+                }
+              }
+#pragma unroll
+              for (int k = 0; k < 7; ++k)
+                if (!((avail7 >> k) & 1u)) tau[k] = 0.0f;
+              const float eta[7] = {S.eta_diag, S.eta_diag, S.eta_lat,      S.eta_lat,
+                                    S.eta_back, S.eta_back_diag, S.eta_back_diag};
+              j = aco_choose7(avail7, tau, S.alpha, eta, w.w1, w.w2);
+            }
+            // candidate j -> move direction: A (+x) 2 3 6 7 1 4 5, B (-x) 4 5 6 7 0 2 3
+            const int q = (int)(((is_a ? 0x5417632u : 0x3207654u) >> (4 * j)) & 0xFu);
+            atomicOr((unsigned long long*)&side[q * R + r], 1ull << c);
+          }
+        } else if (!fwd && (avail & (avail - 1u)) != 0u) {  // two or more side candidates: a choice
           int req;
           if (MODE == 0) {
             req = lem_choose(avail, w.w1, w.w2);
@@ -380,7 +498,36 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
     }
 
     // ---- 3. gather: requesters of every cell, by direction -----------------
-    if (mask_wave) {
+    if (NB8 && mask_wave) {
+      uint64_t own[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) own[q] = rq[q] | ((nq > 0 && row_lane) ? side[q * R + lane] : 0ull);
+      own[0] |= fA;  // forward moves: A by (+1, 0), B by (-1, 0)
+      own[1] |= fB;
+      Wt[0] = own[0] << 1;
+      Wt[1] = own[1] >> 1;
+      Wt[2] = from_down(own[2]) << 1;
+      Wt[3] = from_up(own[3]) << 1;
+      Wt[4] = from_down(own[4]) >> 1;
+      Wt[5] = from_up(own[5]) >> 1;
+      Wt[6] = from_down(own[6]);
+      Wt[7] = from_up(own[7]);
+      uint64_t ones = 0ull, twos = 0ull;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        twos |= ones & Wt[q];
+        ones |= Wt[q];
+      }
+      if (row_lane) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) reqm[q * R + lane] = Wt[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) Wt[q] &= ~twos;  // uncontested winners
+      const int na = enqueue_row_bits(queue, ones, lane);
+      if (lane == 0) ctl[1] = (uint32_t)na;
+    }
+    if (!NB8 && mask_wave) {
       uint64_t own[6];
 #pragma unroll
       for (int q = 0; q < 6; ++q) own[q] = rq[q] | ((nq > 0 && row_lane) ? side[q * R + lane] : 0ull);
@@ -459,7 +606,8 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
           const bool diagonal = best >= 2 && best <= 5;
           const float len = tlen[sr * 64 + sc] + (diagonal ? S.step_diag : 1.0f);
           tlen[r * 64 + c] = len;
-          const bool ga = best == 0 || best == 2 || best == 3 || (best >= 6 && ((H(s, 0, sr) >> sc) & 1ull));
+          const bool ga = NB8 ? (bool)((H(s, 0, sr) >> sc) & 1ull)
+                              : (best == 0 || best == 2 || best == 3 || (best >= 6 && ((H(s, 0, sr) >> sc) & 1ull)));
           const int gp = ga ? 0 : 1;
           float* tp = ga ? tau_a : tau_b;
           int owed = s + 1;  // evaporations since the cell's last deposit, this step's included
@@ -477,7 +625,26 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
     }
 
     // ---- 5. commit: next occupancy, recorded in the history ---------------
-    if (mask_wave) {
+    if (NB8 && mask_wave) {
+      if (na > 0 && row_lane) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Wt[q] |= cwin[q * R + lane];
+      }
+      const uint64_t Au = from_up(A), Ad = from_down(A);
+      const uint64_t in_all = Wt[0] | Wt[1] | Wt[2] | Wt[3] | Wt[4] | Wt[5] | Wt[6] | Wt[7];
+      const uint64_t in_a = (Wt[0] & (A << 1)) | (Wt[1] & (A >> 1)) | (Wt[2] & (Ad << 1)) | (Wt[3] & (Au << 1)) |
+                            (Wt[4] & (Ad >> 1)) | (Wt[5] & (Au >> 1)) | (Wt[6] & Ad) | (Wt[7] & Au);
+      const uint64_t out = (Wt[0] >> 1) | (Wt[1] << 1) | (from_up(Wt[2]) >> 1) | (from_down(Wt[3]) >> 1) |
+                           (from_up(Wt[4]) << 1) | (from_down(Wt[5]) << 1) | from_up(Wt[6]) | from_down(Wt[7]);
+      A = (A & ~out) | in_a;
+      B = (B & ~out) | (in_all & ~in_a);
+      moved_in = in_all;
+      if (row_lane) {
+        H(s + 1, 0, lane) = A;
+        H(s + 1, 1, lane) = B;
+      }
+    }
+    if (!NB8 && mask_wave) {
       if (na > 0 && row_lane) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) Wt[q] |= cwin[q * R + lane];

@@ -75,6 +75,7 @@ def lib() -> ctypes.CDLL:
         L.sim_step_aco.argtypes = [vp, i32, vp]
         L.sim_step_aco_tour.argtypes = [vp, i32, vp]
         L.sim_attach_tour.argtypes = [vp, vp, vp, vp]
+        L.sim_set_neighbours.argtypes = [vp, i32]
         L.sim_stats.argtypes = [vp, P(SimStats), vp]
         L.sim_read_state.argtypes = [vp, vp, vp, vp, vp]
         L.sim_step_timed.argtypes = [vp, i32, i32, vp, P(ctypes.c_double), P(ctypes.c_int64), i32]
@@ -88,7 +89,8 @@ def lib() -> ctypes.CDLL:
         L.sim_destroy.argtypes = [vp]
         L.sim_destroy.restype = None
         for name in ("sim_scratch_bytes", "sim_create", "sim_step_lem", "sim_step_aco",
-                     "sim_step_aco_tour", "sim_attach_tour", "sim_stats", "sim_read_state"):
+                     "sim_step_aco_tour", "sim_attach_tour", "sim_set_neighbours", "sim_stats",
+                     "sim_read_state"):
             getattr(L, name).restype = ctypes.c_int
         _bind_batch(L)
         _lib = L
@@ -166,6 +168,10 @@ def sim_step_aco(h, nsteps: int, stream=None) -> None:
 
 def sim_attach_tour(h, tour, tour_shadow, stream=None) -> None:
     _check(lib().sim_attach_tour(h, _ptr(tour), _ptr(tour_shadow), _stream(stream)), "sim_attach_tour")
+
+
+def sim_set_neighbours(h, n: int) -> None:
+    _check(lib().sim_set_neighbours(h, int(n)), "sim_set_neighbours")
 
 
 def sim_step_aco_tour(h, nsteps: int, stream=None) -> None:
@@ -301,6 +307,8 @@ class Sim:
         torch.cuda.synchronize(self.device)
         self.h = sim_create(self.params, self.code, self.ids, self.tau, self.scratch, nbytes,
                             stream)
+        if getattr(scenario, "neighbours", 5) != 5:
+            sim_set_neighbours(self.h, scenario.neighbours)
         # tour variant: the tour matrix (one float per agent) and its ping-pong half
         self.tour = self.tour_shadow = None
         if scenario.mode == SIM_MODE_ACO_TOUR or getattr(scenario, "tour", None) is not None:

@@ -24,7 +24,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("sim_create", "sim_step_lem", "sim_step_aco", "sim_stats", "sim_scratch_bytes",
               "sim_read_state", "sim_destroy", "sim_strerror", "sim_attach_tour",
-              "sim_step_aco_tour"):
+              "sim_step_aco_tour", "sim_set_neighbours"):
         assert n in names
 
 
@@ -128,3 +128,4 @@ def test_tour_calls_reject_null_handle():
     L = pedsim.lib()
     assert L.sim_step_aco_tour(None, 1, None) == pedsim.SIM_EINVAL
     assert L.sim_attach_tour(None, None, None, None) == pedsim.SIM_EINVAL
+    assert L.sim_set_neighbours(None, 8) == pedsim.SIM_EINVAL
