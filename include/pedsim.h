@@ -253,6 +253,13 @@ int sim_batch_set_tuning(sim_batch* b, int32_t nw, int32_t rows, int32_t steps_p
                          int32_t wgs_per_cu, int32_t use_graph);
 int sim_batch_get_tuning(sim_batch* b, int32_t out[6]);
 
+/* Candidate set of every scenario of the batch (see sim_set_neighbours):
+ * n = 5 (default) or 8. With 8 the batch runs the row-lane engine with the
+ * pheromone in LDS (nw = 0); the call resets the tuning to that set's
+ * default. SIM_EINVAL for other n or a resident scenario whose geometry
+ * does not fit. */
+int sim_batch_set_neighbours(sim_batch* b, int32_t n);
+
 /* Release the batch (not the caller's buffers). NULL is ignored. */
 void sim_batch_destroy(sim_batch* b);
 

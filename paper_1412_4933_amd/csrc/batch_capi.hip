@@ -64,6 +64,7 @@ struct sim_batch {
   Tiling tl;
   int wgs_per_cu;
   int use_graph;
+  bool nb8;  // every scenario uses the eight-neighbour candidate set
   hipGraphExec_t graphs[kBatchMaxLaunches + 1];
 
   BatchPlan plan() const {
@@ -76,6 +77,7 @@ struct sim_batch {
     P.capacity = capacity;
     P.k = tl.steps;
     P.rows = tl.rows;
+    P.nb8 = nb8 ? 1 : 0;
     return P;
   }
   void drop_graphs() {
@@ -89,15 +91,20 @@ struct sim_batch {
 
 namespace {
 
-Tiling default_batch_tiling() {
+// The eight-neighbour set runs on the row-lane engine with the pheromone in
+// LDS: two 512-thread workgroups per compute unit.
+Tiling default_batch_tiling(bool nb8 = false) {
   static const Tiling opts[] = {{3, 56, 3, 256}, {0, 48, 3, 512}, {1, 32, 1, 256}};
-  for (const Tiling& t : opts)
-    if (tiling_valid(t, kModeAco, max_dynamic_lds() - kBatchItemBytes)) return t;
-  return opts[2];
+  static const Tiling opts8[] = {{0, 48, 3, 512}, {0, 40, 2, 512}, {0, 32, 1, 256}};
+  const Tiling* o = nb8 ? opts8 : opts;
+  for (int i = 0; i < 3; ++i)
+    if (tiling_valid(o[i], kModeAco, max_dynamic_lds() - kBatchItemBytes, nb8)) return o[i];
+  return o[2];
 }
 
-bool slot_geometry(const Tiling& tl, HostSlot& hs) {
+bool slot_geometry(const Tiling& tl, HostSlot& hs, bool nb8) {
   Scenario S = base_scenario(&hs.p);
+  S.neighbours = nb8 ? 8 : 5;
   set_geometry(S, tl);
   if (S.tiles_x * S.tiles_y > hs.L.stats_cap) return false;
   S.tile_stats = hs.stats;
@@ -223,6 +230,7 @@ int sim_batch_create(int32_t capacity, void* d_workspace, size_t workspace_bytes
   b->tl = default_batch_tiling();
   b->wgs_per_cu = 4;  // the default streaming tiling needs ~36 KB of LDS: four workgroups fit a CU
   b->use_graph = 1;
+  b->nb8 = false;
   for (int i = 0; i <= kBatchMaxLaunches; ++i) b->graphs[i] = nullptr;
   b->slots.resize(capacity);
   hipError_t e = hipHostMalloc((void**)&b->staging, L.upload, hipHostMallocDefault);
@@ -277,7 +285,7 @@ int sim_batch_add(sim_batch* b, const sim_params* p, int32_t mode, uint8_t* d_co
   hs.stats = (uint32_t*)(scratch + L.stats);
   hs.totals = (unsigned long long*)(scratch + L.totals);
   hs.t = p->step0;
-  if (!slot_geometry(b->tl, hs)) return SIM_EINVAL;
+  if (!slot_geometry(b->tl, hs, b->nb8)) return SIM_EINVAL;
   PEDSIM_HIP(launch_count(d_code, p->W, p->H, p->cross_a, p->cross_b, hs.stats, &hs.stats_entries, s));
   hs.used = true;
   b->slots[free_slot] = hs;
@@ -345,17 +353,35 @@ int sim_batch_set_tuning(sim_batch* b, int32_t nw, int32_t rows, int32_t steps_p
                          int32_t wgs_per_cu, int32_t use_graph) {
   if (!b || wgs_per_cu < 1 || wgs_per_cu > 32) return SIM_EINVAL;
   const Tiling tl{nw, rows, steps_per_launch, threads};
-  if (!tiling_valid(tl, kModeAco, max_dynamic_lds() - kBatchItemBytes)) return SIM_EINVAL;
+  if (!tiling_valid(tl, kModeAco, max_dynamic_lds() - kBatchItemBytes, b->nb8)) return SIM_EINVAL;
   for (int i = 0; i < b->capacity; ++i) {
     if (!b->slots[i].used) continue;
     HostSlot probe = b->slots[i];
-    if (!slot_geometry(tl, probe)) return SIM_EINVAL;
+    if (!slot_geometry(tl, probe, b->nb8)) return SIM_EINVAL;
   }
   b->tl = tl;
   for (int i = 0; i < b->capacity; ++i)
-    if (b->slots[i].used) slot_geometry(tl, b->slots[i]);
+    if (b->slots[i].used) slot_geometry(tl, b->slots[i], b->nb8);
   b->wgs_per_cu = wgs_per_cu;
   b->use_graph = use_graph ? 1 : 0;
+  b->drop_graphs();
+  return SIM_OK;
+}
+
+int sim_batch_set_neighbours(sim_batch* b, int32_t n) {
+  if (!b || (n != 5 && n != 8)) return SIM_EINVAL;
+  const bool nb8 = n == 8;
+  const Tiling tl = default_batch_tiling(nb8);
+  for (int i = 0; i < b->capacity; ++i) {
+    if (!b->slots[i].used) continue;
+    HostSlot probe = b->slots[i];
+    if (!slot_geometry(tl, probe, nb8)) return SIM_EINVAL;
+  }
+  b->nb8 = nb8;
+  b->tl = tl;
+  b->wgs_per_cu = nb8 ? 2 : 4;
+  for (int i = 0; i < b->capacity; ++i)
+    if (b->slots[i].used) slot_geometry(tl, b->slots[i], nb8);
   b->drop_graphs();
   return SIM_OK;
 }

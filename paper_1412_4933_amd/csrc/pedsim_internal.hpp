@@ -136,6 +136,7 @@ struct BatchPlan {
   int capacity;
   int k;                      // steps per launch
   int rows;                   // region rows
+  int nb8;                    // every scenario uses the eight-neighbour set (row-lane engine, nw = 0)
 };
 
 constexpr int kBatchMaxLaunches = 128;  // launches per captured graph

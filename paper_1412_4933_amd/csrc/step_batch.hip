@@ -91,10 +91,10 @@ __global__ __launch_bounds__(1024) void batch_kernel(BatchPlan P, int j) {
 }
 
 // The same with the row-lane engine (regions of 64 columns).
-template <bool STREAM>
+template <bool STREAM, bool NB8 = false>
 __global__ __launch_bounds__(kRowsMaxThreads, kRowsMinWavesPerSimd) void batch_rows_kernel(BatchPlan P, int j) {
   extern __shared__ __align__(16) uint8_t smem[];
-  int& s_item = *(int*)(smem + RowsLayout{P.rows, P.k, true, STREAM}.bytes());
+  int& s_item = *(int*)(smem + RowsLayout{P.rows, P.k, true, STREAM, false, NB8}.bytes());
   const int count = P.counts[j];
   const int total = P.totals[j];
   const BatchEntry* E = P.entries + (size_t)j * P.capacity;
@@ -112,9 +112,9 @@ __global__ __launch_bounds__(kRowsMaxThreads, kRowsMinWavesPerSimd) void batch_r
     const ItemView v = item_view(P, E, lo, item, j);
     const int tx = v.tile % v.S.tiles_x, ty = v.tile / v.S.tiles_x;
     if (v.mode == kModeAco)
-      advance_tile_rows<kModeAco, STREAM>(v.S, smem, P.rows, P.k, tx, ty, v.tile, v.t0, v.steps, v.last);
+      advance_tile_rows<kModeAco, STREAM, NB8>(v.S, smem, P.rows, P.k, tx, ty, v.tile, v.t0, v.steps, v.last);
     else
-      advance_tile_rows<kModeLem, STREAM>(v.S, smem, P.rows, P.k, tx, ty, v.tile, v.t0, v.steps, v.last);
+      advance_tile_rows<kModeLem, STREAM, NB8>(v.S, smem, P.rows, P.k, tx, ty, v.tile, v.t0, v.steps, v.last);
   }
 }
 
@@ -157,6 +157,8 @@ void prepare_batch_kernels() {
                             max_dynamic_lds());
   (void)hipFuncSetAttribute((const void*)batch_rows_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             max_dynamic_lds());
+  (void)hipFuncSetAttribute((const void*)batch_rows_kernel<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            max_dynamic_lds());
   (void)hipGetLastError();  // an unsupported attribute value must not linger as the last error
   done = true;
 }
@@ -169,6 +171,12 @@ static hipError_t launch_batch_nw(const BatchPlan& P, const Tiling& tl, int j, i
 }
 
 hipError_t launch_batch(const BatchPlan& P, const Tiling& tl, int j, int grid, hipStream_t s) {
+  if (P.nb8) {
+    if (tl.nw != 0) return hipErrorInvalidValue;
+    const size_t lds = RowsLayout{tl.rows, tl.steps, true, false, false, true}.bytes() + kBatchItemBytes;
+    batch_rows_kernel<false, true><<<grid, tl.threads, lds, s>>>(P, j);
+    return hipGetLastError();
+  }
   if (rows_engine(tl)) {
     const size_t lds = RowsLayout{tl.rows, tl.steps, true, rows_stream(tl)}.bytes() + kBatchItemBytes;
     if (rows_stream(tl))

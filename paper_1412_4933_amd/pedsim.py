@@ -109,11 +109,12 @@ def _bind_batch(L):
     L.sim_batch_stats.argtypes = [vp, i32, P(SimStats), vp]
     L.sim_batch_set_tuning.argtypes = [vp, i32, i32, i32, i32, i32, i32]
     L.sim_batch_get_tuning.argtypes = [vp, P(i32)]
+    L.sim_batch_set_neighbours.argtypes = [vp, i32]
     L.sim_batch_destroy.argtypes = [vp]
     L.sim_batch_destroy.restype = None
     for name in ("sim_batch_workspace_bytes", "sim_batch_create", "sim_batch_add", "sim_batch_remove",
                  "sim_batch_step", "sim_batch_step_slots", "sim_batch_stats", "sim_batch_set_tuning",
-                 "sim_batch_get_tuning"):
+                 "sim_batch_get_tuning", "sim_batch_set_neighbours"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -271,6 +272,10 @@ def sim_batch_get_tuning(b):
     out = (ctypes.c_int32 * 6)()
     _check(lib().sim_batch_get_tuning(b, out), "sim_batch_get_tuning")
     return tuple(int(v) for v in out)
+
+
+def sim_batch_set_neighbours(b, n: int) -> None:
+    _check(lib().sim_batch_set_neighbours(b, int(n)), "sim_batch_set_neighbours")
 
 
 def sim_batch_destroy(b) -> None:
@@ -445,6 +450,9 @@ class Batch:
 
     def tuning(self):
         return sim_batch_get_tuning(self.b)
+
+    def set_neighbours(self, n: int) -> None:
+        sim_batch_set_neighbours(self.b, n)
 
     def close(self) -> None:
         if self.b:

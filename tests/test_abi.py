@@ -129,3 +129,4 @@ def test_tour_calls_reject_null_handle():
     assert L.sim_step_aco_tour(None, 1, None) == pedsim.SIM_EINVAL
     assert L.sim_attach_tour(None, None, None, None) == pedsim.SIM_EINVAL
     assert L.sim_set_neighbours(None, 8) == pedsim.SIM_EINVAL
+    assert L.sim_batch_set_neighbours(None, 8) == pedsim.SIM_EINVAL
