@@ -208,11 +208,13 @@ const char* sim_kernel_name(int32_t kind);
 void sim_destroy(sim_handle* h);
 
 /*
- * Batched form: many independent scenarios (any sizes, LEM or ACO each)
+ * Batched form: many independent scenarios (any sizes; LEM, ACO or the tour
+ * variant each)
  * advanced together by one persistent kernel per launch, whose work items are
  * (scenario, tile) pairs claimed from a counter; a call's launch sequence is
  * captured once in a hipGraph and replayed. Every scenario's results are
- * bit-identical to running it alone through sim_step_lem / sim_step_aco.
+ * bit-identical to running it alone through sim_step_lem / sim_step_aco /
+ * sim_step_aco_tour.
  */
 typedef struct sim_batch sim_batch;
 
@@ -224,7 +226,8 @@ int sim_batch_workspace_bytes(int32_t capacity, size_t* out);
 int sim_batch_create(int32_t capacity, void* d_workspace, size_t workspace_bytes, sim_batch** out);
 
 /* Add a scenario: same planes, scratch (sim_scratch_bytes) and validation as
- * sim_create; mode (SIM_MODE_LEM / SIM_MODE_ACO) is fixed for the scenario.
+ * sim_create; mode (SIM_MODE_LEM / SIM_MODE_ACO / SIM_MODE_ACO_TOUR) is fixed
+ * for the scenario.
  * Writes its slot index. SIM_EFULL when no slot is free. Synchronises. */
 int sim_batch_add(sim_batch* b, const sim_params* p, int32_t mode, uint8_t* d_code, uint32_t* d_id, float* d_tau,
                   void* d_scratch, size_t scratch_bytes, void* stream, int32_t* slot);
@@ -252,6 +255,13 @@ int sim_batch_stats(sim_batch* b, int32_t slot, sim_stats_t* out, void* stream);
 int sim_batch_set_tuning(sim_batch* b, int32_t nw, int32_t rows, int32_t steps_per_launch, int32_t threads,
                          int32_t wgs_per_cu, int32_t use_graph);
 int sim_batch_get_tuning(sim_batch* b, int32_t out[6]);
+
+/* Tour arrays of a tour-variant slot (added with mode SIM_MODE_ACO_TOUR),
+ * with the meaning, validation and errors of sim_attach_tour. A batch takes
+ * tour-variant scenarios only with a tuning of nw = 0 (sim_batch_add returns
+ * SIM_EINVAL otherwise), and its later tunings must leave room for the tour
+ * lengths in LDS. */
+int sim_batch_attach_tour(sim_batch* b, int32_t slot, float* d_tour, float* d_tour_shadow, void* stream);
 
 /* Candidate set of every scenario of the batch (see sim_set_neighbours):
  * n = 5 (default) or 8. With 8 the batch runs the row-lane engine with the

@@ -31,6 +31,7 @@ struct HostSlot {
   unsigned long long* totals = nullptr;
   int stats_entries = 0;
   uint64_t t = 0;
+  uint64_t agents = 0;
 };
 
 // Byte offsets of the tables inside the workspace (and the staging copy).
@@ -64,7 +65,8 @@ struct sim_batch {
   Tiling tl;
   int wgs_per_cu;
   int use_graph;
-  bool nb8;  // every scenario uses the eight-neighbour candidate set
+  bool nb8;   // every scenario uses the eight-neighbour candidate set
+  bool tour;  // a tour-variant scenario has been added (the LDS layout holds tour lengths)
   hipGraphExec_t graphs[kBatchMaxLaunches + 1];
 
   BatchPlan plan() const {
@@ -78,6 +80,7 @@ struct sim_batch {
     P.k = tl.steps;
     P.rows = tl.rows;
     P.nb8 = nb8 ? 1 : 0;
+    P.tour = tour ? 1 : 0;
     return P;
   }
   void drop_graphs() {
@@ -93,12 +96,13 @@ namespace {
 
 // The eight-neighbour set runs on the row-lane engine with the pheromone in
 // LDS: two 512-thread workgroups per compute unit.
-Tiling default_batch_tiling(bool nb8 = false) {
+Tiling default_batch_tiling(bool lds_form = false) {
   static const Tiling opts[] = {{3, 56, 3, 256}, {0, 48, 3, 512}, {1, 32, 1, 256}};
   static const Tiling opts8[] = {{0, 48, 3, 512}, {0, 40, 2, 512}, {0, 32, 1, 256}};
-  const Tiling* o = nb8 ? opts8 : opts;
+  const Tiling* o = lds_form ? opts8 : opts;
   for (int i = 0; i < 3; ++i)
-    if (tiling_valid(o[i], kModeAco, max_dynamic_lds() - kBatchItemBytes, nb8)) return o[i];
+    if (tiling_valid(o[i], lds_form ? kModeAcoTour : kModeAco, max_dynamic_lds() - kBatchItemBytes, lds_form))
+      return o[i];
   return o[2];
 }
 
@@ -175,6 +179,9 @@ int run_chunk(sim_batch* b, const std::vector<int>& steps, hipStream_t s) {
     d.id[1] = x.shadow.id;
     d.tau[0] = x.user.tau;
     d.tau[1] = x.shadow.tau;
+    d.tour[0] = x.user.tour;
+    d.tour[1] = x.shadow.tour;
+    d.agents = (uint32_t)x.agents;
     d.t0 = x.t;
     d.steps = steps[i];
     d.mode = x.mode;
@@ -231,6 +238,7 @@ int sim_batch_create(int32_t capacity, void* d_workspace, size_t workspace_bytes
   b->wgs_per_cu = 4;  // the default streaming tiling needs ~36 KB of LDS: four workgroups fit a CU
   b->use_graph = 1;
   b->nb8 = false;
+  b->tour = false;
   for (int i = 0; i <= kBatchMaxLaunches; ++i) b->graphs[i] = nullptr;
   b->slots.resize(capacity);
   hipError_t e = hipHostMalloc((void**)&b->staging, L.upload, hipHostMallocDefault);
@@ -260,9 +268,13 @@ int sim_batch_add(sim_batch* b, const sim_params* p, int32_t mode, uint8_t* d_co
   if (!b || !slot) return SIM_EINVAL;
   int e = check_params(p);
   if (e) return e;
-  if (mode != kModeLem && mode != kModeAco) return SIM_EINVAL;
+  if (mode != kModeLem && mode != kModeAco && mode != kModeAcoTour) return SIM_EINVAL;
   if (!d_code || !d_id) return SIM_EINVAL;
-  if (mode == kModeAco && !d_tau) return SIM_ENOTAU;
+  if (mode != kModeLem && !d_tau) return SIM_ENOTAU;
+  if (mode == kModeAcoTour) {  // the row-lane engine with the pheromone and tour lengths in LDS
+    if (b->tl.nw != 0 || !tiling_valid(b->tl, kModeAcoTour, max_dynamic_lds() - kBatchItemBytes, b->nb8))
+      return SIM_EINVAL;
+  }
   const ScratchLayout L = layout_of(p);
   if (!d_scratch || scratch_bytes < L.total) return SIM_ESCRATCH;
   int free_slot = -1;
@@ -274,9 +286,11 @@ int sim_batch_add(sim_batch* b, const sim_params* p, int32_t mode, uint8_t* d_co
   if (free_slot < 0) return SIM_EFULL;
   hipStream_t s = (hipStream_t)stream;
   uint8_t* scratch = (uint8_t*)d_scratch;
-  e = validate_state(p, d_code, d_id, d_tau, scratch, L, s);
+  uint64_t agents = 0;
+  e = validate_state(p, d_code, d_id, d_tau, scratch, L, s, &agents);
   if (e) return e;
   HostSlot hs;
+  hs.agents = agents;
   hs.p = *p;
   hs.mode = mode;
   hs.user = Planes{d_code, d_id, d_tau};
@@ -289,6 +303,10 @@ int sim_batch_add(sim_batch* b, const sim_params* p, int32_t mode, uint8_t* d_co
   PEDSIM_HIP(launch_count(d_code, p->W, p->H, p->cross_a, p->cross_b, hs.stats, &hs.stats_entries, s));
   hs.used = true;
   b->slots[free_slot] = hs;
+  if (mode == kModeAcoTour && !b->tour) {
+    b->tour = true;
+    b->drop_graphs();  // the launches now reserve LDS for tour lengths
+  }
   *slot = free_slot;
   return SIM_OK;
 }
@@ -305,6 +323,8 @@ int sim_batch_step_slots(sim_batch* b, const int32_t* steps, int32_t n, void* st
   for (int i = 0; i < n; ++i) {
     if (steps[i] < 0) return SIM_EINVAL;
     if (steps[i] > 0 && !b->slots[i].used) return SIM_EINVAL;
+    if (steps[i] > 0 && b->slots[i].mode == kModeAcoTour && b->slots[i].agents > 0 && !b->slots[i].user.tour)
+      return SIM_ENOTOUR;
     remaining[i] = steps[i];
   }
   hipStream_t s = (hipStream_t)stream;
@@ -353,7 +373,8 @@ int sim_batch_set_tuning(sim_batch* b, int32_t nw, int32_t rows, int32_t steps_p
                          int32_t wgs_per_cu, int32_t use_graph) {
   if (!b || wgs_per_cu < 1 || wgs_per_cu > 32) return SIM_EINVAL;
   const Tiling tl{nw, rows, steps_per_launch, threads};
-  if (!tiling_valid(tl, kModeAco, max_dynamic_lds() - kBatchItemBytes, b->nb8)) return SIM_EINVAL;
+  if (!tiling_valid(tl, b->tour ? kModeAcoTour : kModeAco, max_dynamic_lds() - kBatchItemBytes, b->nb8))
+    return SIM_EINVAL;
   for (int i = 0; i < b->capacity; ++i) {
     if (!b->slots[i].used) continue;
     HostSlot probe = b->slots[i];
@@ -368,10 +389,30 @@ int sim_batch_set_tuning(sim_batch* b, int32_t nw, int32_t rows, int32_t steps_p
   return SIM_OK;
 }
 
+int sim_batch_attach_tour(sim_batch* b, int32_t slot, float* d_tour, float* d_tour_shadow, void* stream) {
+  if (!b || slot < 0 || slot >= b->capacity || !b->slots[slot].used) return SIM_EINVAL;
+  HostSlot& x = b->slots[slot];
+  if (x.mode != kModeAcoTour) return SIM_EINVAL;
+  if (x.agents > 0 && (!d_tour || !d_tour_shadow || d_tour == d_tour_shadow)) return SIM_EINVAL;
+  if (x.agents > 0) {
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* counters = x.totals + kTileStatFields;
+    unsigned long long host_counters[3];
+    PEDSIM_HIP(hipMemsetAsync(counters, 0, 3 * sizeof(unsigned long long), s));
+    PEDSIM_HIP(launch_validate_values(d_tour, (size_t)x.agents, counters, s));
+    PEDSIM_HIP(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s));
+    PEDSIM_HIP(hipStreamSynchronize(s));
+    if (host_counters[2]) return SIM_ESTATE;
+  }
+  x.user.tour = d_tour;
+  x.shadow.tour = d_tour_shadow;
+  return SIM_OK;
+}
+
 int sim_batch_set_neighbours(sim_batch* b, int32_t n) {
   if (!b || (n != 5 && n != 8)) return SIM_EINVAL;
   const bool nb8 = n == 8;
-  const Tiling tl = default_batch_tiling(nb8);
+  const Tiling tl = default_batch_tiling(nb8 || b->tour);
   for (int i = 0; i < b->capacity; ++i) {
     if (!b->slots[i].used) continue;
     HostSlot probe = b->slots[i];
@@ -379,7 +420,7 @@ int sim_batch_set_neighbours(sim_batch* b, int32_t n) {
   }
   b->nb8 = nb8;
   b->tl = tl;
-  b->wgs_per_cu = nb8 ? 2 : 4;
+  b->wgs_per_cu = (nb8 || b->tour) ? 2 : 4;
   for (int i = 0; i < b->capacity; ++i)
     if (b->slots[i].used) slot_geometry(tl, b->slots[i], nb8);
   b->drop_graphs();

@@ -114,9 +114,11 @@ struct BatchSlot {
   uint8_t* code[2];   // [0] caller planes, [1] shadow planes in the slot's scratch
   uint32_t* id[2];
   float* tau[2];
+  float* tour[2];     // tour variant: tour matrices (caller's, shadow), one float per agent
   uint64_t t0;        // index of the slot's first step in this call
   int steps;          // steps the slot runs in this call (0: idle)
-  int mode;           // kModeLem or kModeAco
+  int mode;           // kModeLem, kModeAco or kModeAcoTour
+  uint32_t agents;    // number of agents (tour matrix entries)
 };
 
 // Launch j of a call processes, in order, the tiles of every slot with
@@ -137,6 +139,7 @@ struct BatchPlan {
   int k;                      // steps per launch
   int rows;                   // region rows
   int nb8;                    // every scenario uses the eight-neighbour set (row-lane engine, nw = 0)
+  int tour;                   // the batch holds tour-variant scenarios (row-lane engine, nw = 0)
 };
 
 constexpr int kBatchMaxLaunches = 128;  // launches per captured graph

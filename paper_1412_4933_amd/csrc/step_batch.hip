@@ -52,6 +52,8 @@ __device__ __forceinline__ ItemView item_view(const BatchPlan& P, const BatchEnt
   v.S.code_out = (uint8_t*)uniform_u64((uint64_t)B.code[par ^ 1]);
   v.S.id_out = (uint32_t*)uniform_u64((uint64_t)B.id[par ^ 1]);
   v.S.tau_out = (float*)uniform_u64((uint64_t)B.tau[par ^ 1]);
+  v.S.tour_in = (const float*)uniform_u64((uint64_t)B.tour[par]);
+  v.S.tour_out = (float*)uniform_u64((uint64_t)B.tour[par ^ 1]);
   const int bsteps = __builtin_amdgcn_readfirstlane(B.steps);
   v.mode = __builtin_amdgcn_readfirstlane(B.mode);
   const int done = j * P.k;
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(1024) void batch_kernel(BatchPlan P, int j) {
 template <bool STREAM, bool NB8 = false>
 __global__ __launch_bounds__(kRowsMaxThreads, kRowsMinWavesPerSimd) void batch_rows_kernel(BatchPlan P, int j) {
   extern __shared__ __align__(16) uint8_t smem[];
-  int& s_item = *(int*)(smem + RowsLayout{P.rows, P.k, true, STREAM, false, NB8}.bytes());
+  int& s_item = *(int*)(smem + RowsLayout{P.rows, P.k, true, STREAM, !STREAM && P.tour != 0, NB8}.bytes());
   const int count = P.counts[j];
   const int total = P.totals[j];
   const BatchEntry* E = P.entries + (size_t)j * P.capacity;
@@ -111,6 +113,12 @@ __global__ __launch_bounds__(kRowsMaxThreads, kRowsMinWavesPerSimd) void batch_r
     }
     const ItemView v = item_view(P, E, lo, item, j);
     const int tx = v.tile % v.S.tiles_x, ty = v.tile / v.S.tiles_x;
+    if constexpr (!STREAM) {
+      if (v.mode == kModeAcoTour) {
+        advance_tile_rows<kModeAcoTour, false, NB8>(v.S, smem, P.rows, P.k, tx, ty, v.tile, v.t0, v.steps, v.last);
+        continue;
+      }
+    }
     if (v.mode == kModeAco)
       advance_tile_rows<kModeAco, STREAM, NB8>(v.S, smem, P.rows, P.k, tx, ty, v.tile, v.t0, v.steps, v.last);
     else
@@ -134,11 +142,13 @@ __global__ __launch_bounds__(256) void batch_copyback_kernel(BatchPlan P) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells; i += stride) {
     B.code[0][i] = B.code[1][i];
     B.id[0][i] = B.id[1][i];
-    if (B.mode == kModeAco) {
+    if (B.mode != kModeLem) {
       B.tau[0][i] = B.tau[1][i];
       B.tau[0][cells + i] = B.tau[1][cells + i];
     }
   }
+  if (B.mode == kModeAcoTour)
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < B.agents; i += stride) B.tour[0][i] = B.tour[1][i];
 }
 
 hipError_t launch_batch_reset(const BatchPlan& P, int launches, hipStream_t s) {
@@ -173,12 +183,14 @@ static hipError_t launch_batch_nw(const BatchPlan& P, const Tiling& tl, int j, i
 hipError_t launch_batch(const BatchPlan& P, const Tiling& tl, int j, int grid, hipStream_t s) {
   if (P.nb8) {
     if (tl.nw != 0) return hipErrorInvalidValue;
-    const size_t lds = RowsLayout{tl.rows, tl.steps, true, false, false, true}.bytes() + kBatchItemBytes;
+    const size_t lds = RowsLayout{tl.rows, tl.steps, true, false, P.tour != 0, true}.bytes() + kBatchItemBytes;
     batch_rows_kernel<false, true><<<grid, tl.threads, lds, s>>>(P, j);
     return hipGetLastError();
   }
+  if (P.tour && tl.nw != 0) return hipErrorInvalidValue;
   if (rows_engine(tl)) {
-    const size_t lds = RowsLayout{tl.rows, tl.steps, true, rows_stream(tl)}.bytes() + kBatchItemBytes;
+    const size_t lds =
+        RowsLayout{tl.rows, tl.steps, true, rows_stream(tl), P.tour != 0 && !rows_stream(tl)}.bytes() + kBatchItemBytes;
     if (rows_stream(tl))
       batch_rows_kernel<true><<<grid, tl.threads, lds, s>>>(P, j);
     else

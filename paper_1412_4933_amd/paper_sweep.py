@@ -11,7 +11,8 @@ random placements and generator, so only the qualitative shape can be
 compared.
 
   python -m paper_1412_4933_amd.paper_sweep [--densities 1-20] [--repeats 10]
-                                             [--steps 25000] [--neighbours 5|8] [--out FILE]
+                                             [--steps 25000] [--neighbours 5|8]
+                                             [--aco constant|tour] [--out FILE]
 
 Prints one JSON document (per-density means, the overall ACO/LEM ratio and
 the run's throughput).
@@ -31,15 +32,18 @@ def parse_range(text: str):
     return [int(v) for v in text.split(",")]
 
 
-def run(densities, repeats: int, steps: int, neighbours: int = 5, log=print):
+def run(densities, repeats: int, steps: int, neighbours: int = 5, aco: str = "constant", log=print):
     import torch
     from . import pedsim
     from . import scenarios as S
 
-    scns = S.paper_sweep(densities, repeats, steps, neighbours=neighbours)
+    aco_mode = S.MODE_ACO_TOUR if aco == "tour" else S.MODE_ACO
+    scns = S.paper_sweep(densities, repeats, steps, modes=(S.MODE_LEM, aco_mode), neighbours=neighbours)
     batch = pedsim.Batch(len(scns))
     if neighbours != 5:
         batch.set_neighbours(neighbours)
+    elif aco_mode == S.MODE_ACO_TOUR:
+        batch.set_tuning(0, 48, 3, 512, 2)  # the tour variant runs on the LDS form
     slots = []
     for s in scns:
         slots.append(batch.add(s))
@@ -73,7 +77,7 @@ def run(densities, repeats: int, steps: int, neighbours: int = 5, log=print):
     tot_aco = sum(t["aco_crossed_mean"] for t in table)
     agent_steps = sum(s.agents for s in scns) * steps
     return {"grid": "480x480", "steps": steps, "repeats": repeats, "densities": list(densities),
-            "neighbours": neighbours,
+            "neighbours": neighbours, "aco_deposit": aco,
             "table": table, "aco_over_lem": (tot_aco / tot_lem) if tot_lem else None,
             "wall_s": wall, "agent_steps_per_s": agent_steps / wall}
 
@@ -85,9 +89,12 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=25000)
     ap.add_argument("--neighbours", type=int, default=5, choices=(5, 8),
                     help="candidate set: 5 (no backward cells) or the paper's full 8")
+    ap.add_argument("--aco", default="constant", choices=("constant", "tour"),
+                    help="ACO deposit: constant dtau on occupied cells, or eq. 5's dtau / L_k "
+                         "on entered cells (the tour variant)")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
-    res = run(parse_range(args.densities), args.repeats, args.steps, args.neighbours,
+    res = run(parse_range(args.densities), args.repeats, args.steps, args.neighbours, args.aco,
               log=lambda *a: print(*a, file=sys.stderr, flush=True))
     text = json.dumps(res)
     if args.out:

@@ -110,11 +110,12 @@ def _bind_batch(L):
     L.sim_batch_set_tuning.argtypes = [vp, i32, i32, i32, i32, i32, i32]
     L.sim_batch_get_tuning.argtypes = [vp, P(i32)]
     L.sim_batch_set_neighbours.argtypes = [vp, i32]
+    L.sim_batch_attach_tour.argtypes = [vp, i32, vp, vp, vp]
     L.sim_batch_destroy.argtypes = [vp]
     L.sim_batch_destroy.restype = None
     for name in ("sim_batch_workspace_bytes", "sim_batch_create", "sim_batch_add", "sim_batch_remove",
                  "sim_batch_step", "sim_batch_step_slots", "sim_batch_stats", "sim_batch_set_tuning",
-                 "sim_batch_get_tuning", "sim_batch_set_neighbours"):
+                 "sim_batch_get_tuning", "sim_batch_set_neighbours", "sim_batch_attach_tour"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -274,6 +275,11 @@ def sim_batch_get_tuning(b):
     return tuple(int(v) for v in out)
 
 
+def sim_batch_attach_tour(b, slot: int, tour, tour_shadow, stream=None) -> None:
+    _check(lib().sim_batch_attach_tour(b, int(slot), _ptr(tour), _ptr(tour_shadow), _stream(stream)),
+           "sim_batch_attach_tour")
+
+
 def sim_batch_set_neighbours(b, n: int) -> None:
     _check(lib().sim_batch_set_neighbours(b, int(n)), "sim_batch_set_neighbours")
 
@@ -385,9 +391,16 @@ class _Resident:
             self.tau = torch.from_numpy(np.ascontiguousarray(scenario.tau)).to(device)
         self.scratch_bytes = sim_scratch_bytes(self.params)
         self.scratch = torch.empty(self.scratch_bytes, dtype=torch.uint8, device=device)
+        self.tour = self.tour_shadow = None
+        if scenario.mode == SIM_MODE_ACO_TOUR:
+            n = int(scenario.ids.max()) if scenario.ids.size else 0
+            t0 = scenario.tour if getattr(scenario, "tour", None) is not None else np.zeros(n, np.float32)
+            self.tour = torch.from_numpy(np.ascontiguousarray(t0, dtype=np.float32)).to(device)
+            self.tour_shadow = torch.empty_like(self.tour)
 
     def nbytes(self) -> int:
         n = self.code.numel() + 4 * self.ids.numel() + self.scratch_bytes
+        n += 8 * self.tour.numel() if self.tour is not None else 0
         return n + (4 * self.tau.numel() if self.tau is not None else 0)
 
     def state(self):
@@ -418,6 +431,8 @@ class Batch:
         self.torch.cuda.synchronize(self.device)
         slot = sim_batch_add(self.b, res.params, mode, res.code, res.ids, res.tau, res.scratch,
                              res.scratch_bytes, self.stream)
+        if res.tour is not None and res.tour.numel():
+            sim_batch_attach_tour(self.b, slot, res.tour, res.tour_shadow, self.stream)
         self.members[slot] = res
         return slot
 
@@ -453,6 +468,12 @@ class Batch:
 
     def set_neighbours(self, n: int) -> None:
         sim_batch_set_neighbours(self.b, n)
+
+    def tour_lengths(self, slot: int) -> np.ndarray:
+        """The tour matrix of a tour-variant slot on the host."""
+        s = self.stream if self.stream is not None else self.torch.cuda.current_stream(self.device)
+        s.synchronize()
+        return self.members[slot].tour.cpu().numpy()
 
     def close(self) -> None:
         if self.b:

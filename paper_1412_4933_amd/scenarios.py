@@ -200,6 +200,13 @@ def aco_tour_1024x512(seed: int = 1) -> Scenario:
                          steps=2000)
 
 
+def aco_nb8_1024x512(seed: int = 1) -> Scenario:
+    """The 1024x512 ACO workload with the paper's full eight-neighbour
+    candidate set (backward cells ranked last)."""
+    return make_scenario(1024, 512, 50000, 50000, band_a=64, seed=seed, mode=MODE_ACO,
+                         steps=2000, neighbours=8)
+
+
 def stress_4096x2048(mode: int = MODE_ACO, seed: int = 1) -> Scenario:
     """4096x2048 with 5% of interior cells covered by 2..16-cell rectangles,
     500,000 agents per group, 1,000 steps."""
@@ -213,9 +220,9 @@ def paper_sweep(densities=range(1, 21), repeats: int = 10, steps: int = 25000,
     grid, 1,280 k agents per group for density k (2,560 k in all), each group
     packed into the narrowest band that holds it (3 columns for k = 1), a
     crossing line at the opposite group's band, `steps` steps, `repeats`
-    placements per density. LEM and ACO runs of one (k, repeat) share their
-    placement and random key (seed 100 k + repeat), so the comparison is
-    paired. Returns the scenarios ordered by (k, repeat, mode)."""
+    placements per density. The runs of one (k, repeat) in each of `modes`
+    share their placement and random key (seed 100 k + repeat), so the
+    comparison is paired. Returns the scenarios ordered by (k, repeat, mode)."""
     out = []
     for k in densities:
         for rep in range(repeats):

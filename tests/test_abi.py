@@ -130,3 +130,4 @@ def test_tour_calls_reject_null_handle():
     assert L.sim_attach_tour(None, None, None, None) == pedsim.SIM_EINVAL
     assert L.sim_set_neighbours(None, 8) == pedsim.SIM_EINVAL
     assert L.sim_batch_set_neighbours(None, 8) == pedsim.SIM_EINVAL
+    assert L.sim_batch_attach_tour(None, 0, None, None, None) == pedsim.SIM_EINVAL

@@ -147,3 +147,53 @@ def test_tour_errors(pedsim):
         pedsim.sim_attach_tour(sim.h, shadow, shadow)
     assert e.value.code == pedsim.SIM_EINVAL
     sim.close()
+
+
+def _batch_mix(neighbours):
+    """Twelve scenarios of the 256-scenario batch's shapes; every third runs
+    the tour variant (with initial tour lengths), the rest LEM or ACO."""
+    scns = S.batched_256(count=12, steps=100)
+    for i, s in enumerate(scns):
+        s.neighbours = neighbours
+        if i % 3 == 2:
+            s.mode = TOUR
+            if s.tau is None:
+                s.tau = np.ones((2, s.H, s.W), np.float32)
+            s.tour = (np.random.default_rng(i).random(s.agents) * 5).astype(np.float32)
+    return scns
+
+
+@pytest.mark.parametrize("neighbours", [5, 8])
+def test_tour_in_a_batch_matches_oracle(pedsim, neighbours):
+    scns = _batch_mix(neighbours)
+    batch = pedsim.Batch(len(scns))
+    if neighbours == 8:
+        batch.set_neighbours(8)
+    else:
+        batch.set_tuning(0, 48, 3, 512, 2)
+    slots = [batch.add(s) for s in scns]
+    say("tour batch", neighbours)
+    batch.step_slots({sl: 40 + 7 * i for i, sl in enumerate(slots)})
+    batch.step(30)
+    for i, (s, sl) in enumerate(zip(scns, slots)):
+        st = oracle.State.from_scenario(s)
+        st.run(s.mode, 40 + 7 * i + 30)
+        code, ids, tau = batch.state(sl)
+        assert np.array_equal(code, st.code) and np.array_equal(ids, st.ids), (i, s.mode)
+        if s.mode != S.MODE_LEM:
+            assert np.array_equal(tau.view(np.uint32), st.tau.view(np.uint32)), i
+        if s.mode == TOUR:
+            assert np.array_equal(batch.tour_lengths(sl).view(np.uint32), st.tour.view(np.uint32)), i
+        got = batch.stats(sl)
+        a, b, ca, cb = st.counts()
+        assert (got["crossed_a"], got["crossed_b"], got["step"]) == (ca, cb, st.t)
+    batch.close()
+
+
+def test_tour_batch_needs_the_lds_form(pedsim):
+    scn = S.make_scenario(64, 32, 100, 100, band_a=6, seed=3, mode=TOUR)
+    batch = pedsim.Batch(2)  # default tuning: the streaming form
+    with pytest.raises(pedsim.SimError) as e:
+        batch.add(scn)
+    assert e.value.code == pedsim.SIM_EINVAL
+    batch.close()
