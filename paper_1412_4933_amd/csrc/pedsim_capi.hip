@@ -130,7 +130,8 @@ namespace {
 // The tour variant runs on the row-lane engine with the pheromone in LDS
 // (its deposits depend on per-move tour lengths, so they are applied in LDS
 // as they happen); its extra per-cell tour lengths make the 56-row shape too
-// big for two workgroups per compute unit, so medium grids use 48 rows.
+// big for two workgroups per compute unit, so medium grids use 48 rows. The
+// eight-neighbour set (LEM, ACO) also needs the pheromone in LDS.
 Tiling default_tiling(int mode, size_t cells, bool nb8 = false) {
   static const Tiling tiny_opts[] = {{0, 48, 6, 512}, {0, 32, 4, 256}, {1, 32, 1, 256}};
   static const Tiling small_opts[] = {{0, 56, 4, 512}, {0, 48, 3, 512}, {1, 32, 1, 256}};
@@ -138,10 +139,14 @@ Tiling default_tiling(int mode, size_t cells, bool nb8 = false) {
   static const Tiling tour_tiny[] = {{0, 48, 6, 512}, {0, 32, 4, 256}, {0, 32, 1, 256}};
   static const Tiling tour_small[] = {{0, 48, 3, 512}, {0, 40, 3, 512}, {0, 32, 1, 256}};
   static const Tiling tour_large[] = {{0, 48, 2, 512}, {0, 40, 2, 256}, {0, 32, 1, 256}};
+  static const Tiling nb8_tiny[] = {{0, 48, 6, 512}, {0, 32, 4, 256}, {0, 32, 1, 256}};
+  static const Tiling nb8_small[] = {{0, 56, 4, 512}, {0, 48, 3, 512}, {0, 32, 1, 256}};
+  static const Tiling nb8_large[] = {{0, 56, 2, 512}, {0, 48, 2, 512}, {0, 32, 1, 256}};
   const int size = cells < ((size_t)1 << 18) ? 0 : (cells < ((size_t)2 << 20) ? 1 : 2);
   const Tiling* const plain[3] = {tiny_opts, small_opts, large_opts};
   const Tiling* const tour[3] = {tour_tiny, tour_small, tour_large};
-  const Tiling* opts = (mode == kModeAcoTour || nb8) ? tour[size] : plain[size];
+  const Tiling* const eight[3] = {nb8_tiny, nb8_small, nb8_large};
+  const Tiling* opts = mode == kModeAcoTour ? tour[size] : (nb8 ? eight[size] : plain[size]);
   for (int i = 0; i < 3; ++i)
     if (tiling_valid(opts[i], mode, max_dynamic_lds(), nb8)) return opts[i];
   return opts[2];
