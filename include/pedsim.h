@@ -260,7 +260,8 @@ int sim_batch_get_tuning(sim_batch* b, int32_t out[6]);
  * with the meaning, validation and errors of sim_attach_tour. A batch takes
  * tour-variant scenarios only with a tuning of nw = 0 (sim_batch_add returns
  * SIM_EINVAL otherwise), and its later tunings must leave room for the tour
- * lengths in LDS. */
+ * lengths in LDS (once a tour-variant scenario has been added, the batch
+ * keeps that room for its lifetime). */
 int sim_batch_attach_tour(sim_batch* b, int32_t slot, float* d_tour, float* d_tour_shadow, void* stream);
 
 /* Candidate set of every scenario of the batch (see sim_set_neighbours):
