@@ -17,7 +17,9 @@ from typing import Dict, Iterable, List, Optional, Sequence, Tuple
 
 from . import pedsim
 
-# (nw, rows, steps per launch, threads); nw = 0 is the row-lane engine
+# (nw, rows, steps per launch, threads); nw = 0 is the row-lane engine. Shapes
+# the library rejects for a workload (the tour variant and the eight-neighbour
+# set take nw = 0 only) are skipped.
 PLAIN_CANDIDATES = [
     (1, 32, 1, 256), (1, 32, 2, 512), (1, 48, 2, 512), (1, 64, 2, 512), (1, 64, 3, 512),
     (1, 96, 2, 1024), (1, 128, 3, 1024), (2, 32, 2, 512), (2, 64, 2, 1024), (2, 64, 3, 1024),
@@ -41,8 +43,10 @@ def _bucket(v: float) -> int:
 
 def signature(scns: Sequence, kind: str) -> str:
     cells = sum(s.W * s.H for s in scns)
-    aco = sum(1 for s in scns if s.mode == 1)
-    return f"{kind}:n{len(scns)}:c{_bucket(cells)}:a{_bucket(aco + 1)}"
+    aco = sum(1 for s in scns if s.mode != 0)
+    tour = sum(1 for s in scns if s.mode == 2)
+    nb = max(getattr(s, "neighbours", 5) for s in scns)
+    return f"{kind}:n{len(scns)}:c{_bucket(cells)}:a{_bucket(aco + 1)}:t{_bucket(tour + 1)}:nb{nb}"
 
 
 def load(path: Optional[str]) -> None:
@@ -101,6 +105,11 @@ def tune_batch(scns: Sequence, steps: int = 20, candidates: Iterable = BATCH_CAN
     timings = []
     batch = pedsim.Batch(len(scns), device=device)
     try:
+        nb = getattr(scns[0], "neighbours", 5) if scns else 5
+        if nb != 5:
+            batch.set_neighbours(nb)
+        elif any(s.mode == 2 for s in scns):
+            batch.set_tuning(0, 48, 3, 512, 2)  # tour scenarios need the LDS form before they are added
         for s in scns:
             batch.add(s)
         for tu in candidates:

@@ -424,9 +424,13 @@ class Batch:
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.b = sim_batch_create(capacity, self.workspace, nbytes)
         self.members = {}
+        self.neighbours = 5
 
     def add(self, scenario, mode: Optional[int] = None, step0: int = 0) -> int:
         mode = scenario.mode if mode is None else mode
+        if getattr(scenario, "neighbours", 5) != self.neighbours:
+            raise ValueError(f"scenario uses {scenario.neighbours} neighbours, the batch "
+                             f"{self.neighbours} (set_neighbours first)")
         res = _Resident(scenario, self.device, step0)
         self.torch.cuda.synchronize(self.device)
         slot = sim_batch_add(self.b, res.params, mode, res.code, res.ids, res.tau, res.scratch,
@@ -467,7 +471,11 @@ class Batch:
         return sim_batch_get_tuning(self.b)
 
     def set_neighbours(self, n: int) -> None:
+        for res in self.members.values():
+            if getattr(res.scenario, "neighbours", 5) != n:
+                raise ValueError("a resident scenario uses another candidate set")
         sim_batch_set_neighbours(self.b, n)
+        self.neighbours = n
 
     def tour_lengths(self, slot: int) -> np.ndarray:
         """The tour matrix of a tour-variant slot on the host."""

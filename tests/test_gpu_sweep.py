@@ -76,3 +76,19 @@ def test_uneven_batch_eight_neighbours_matches_oracle():
         s.neighbours = 8
     print("[gpu-case] uneven batch nb8", len(scns), flush=True)
     _batch_vs_oracle(pedsim, scns, 100, 8)
+
+
+def test_batch_rejects_a_scenario_of_another_candidate_set():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1412_4933_amd import pedsim
+    s8 = S.make_scenario(64, 32, 50, 50, band_a=4, seed=2, mode=S.MODE_LEM, neighbours=8)
+    s5 = S.make_scenario(64, 32, 50, 50, band_a=4, seed=2, mode=S.MODE_LEM)
+    batch = pedsim.Batch(2)
+    with pytest.raises(ValueError):
+        batch.add(s8)
+    batch.add(s5)
+    with pytest.raises(ValueError):
+        batch.set_neighbours(8)  # a resident scenario uses five candidates
+    batch.close()
