@@ -139,3 +139,26 @@ def test_batch_long_call_splits_and_slots_are_reused(pedsim):
     check_slot(batch, new_slot, st4, "reused slot")
     check_slot(batch, slots[0], st[0], "neighbour of reused slot")
     batch.close()
+
+
+def test_full_256_scenario_batch_sampled_against_oracle(pedsim):
+    """The benchmark's batch at full size (256 scenarios, 3.24M agents, the
+    default tuning and graph replay): every counter is checked against the
+    oracle's invariants, and sampled scenarios (the three largest, the three
+    smallest and six others) bit for bit."""
+    scns = S.batched_256(steps=60)
+    batch = pedsim.Batch(len(scns))
+    slots = [batch.add(s) for s in scns]
+    say("full batch", len(scns), batch.tuning())
+    batch.step(60)
+    for s, slot in zip(scns, slots):
+        got = batch.stats(slot)
+        assert (got["agents_a"], got["agents_b"], got["step"]) == (s.n_a, s.n_b, 60)
+    order = sorted(range(len(scns)), key=lambda i: scns[i].agents)
+    rng = np.random.default_rng(7)
+    sample = order[:3] + order[-3:] + [int(i) for i in rng.choice(order[3:-3], 6, replace=False)]
+    for i in sample:
+        st = oracle.State.from_scenario(scns[i])
+        st.run(scns[i].mode, 60)
+        check_slot(batch, slots[i], st, f"scenario {i} ({scns[i].W}x{scns[i].H}, {scns[i].agents} agents)")
+    batch.close()
