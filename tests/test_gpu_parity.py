@@ -172,8 +172,9 @@ def test_aco_1024x512_full_run(pedsim, tiling):
 
 @pytest.mark.parametrize("mode", [S.MODE_LEM, S.MODE_ACO])
 def test_stress_4096x2048_first_steps(pedsim, mode):
-    """Full-size stress grid: bit-exact for the first steps, then invariants
-    that hold at any size over a longer GPU run."""
+    """Full-size stress grid in the benchmark's launch configuration:
+    bit-exact after 15 and after 100 steps, then invariants that hold at any
+    size over a longer GPU run."""
     scn = S.stress_4096x2048(mode)
     say("stress 4096x2048", mode)
     sim = pedsim.Sim(scn)
@@ -182,6 +183,9 @@ def test_stress_4096x2048_first_steps(pedsim, mode):
         sim.step(c, mode)
         st.run(mode, c)
     assert_same(sim, st, "stress after 15 steps")
+    sim.step(85, mode)
+    st.run(mode, 85)
+    assert_same(sim, st, "stress after 100 steps")
     sim.step(300, mode)
     code, ids, tau = sim.state()
     assert np.array_equal(code == S.WALL, scn.code == S.WALL)
