@@ -129,16 +129,16 @@ namespace {
 // fits the device's LDS is used.
 // The tour variant runs on the row-lane engine with the pheromone in LDS
 // (its deposits depend on per-move tour lengths, so they are applied in LDS
-// as they happen); its extra per-cell tour lengths make the 56-row shape too
-// big for two workgroups per compute unit, so medium grids use 48 rows. The
-// eight-neighbour set (LEM, ACO) also needs the pheromone in LDS.
+// as they happen; its per-cell tour lengths take the LDS of the contest
+// tickets, which it draws again instead). The eight-neighbour set (LEM, ACO)
+// also needs the pheromone in LDS.
 Tiling default_tiling(int mode, size_t cells, bool nb8 = false) {
   static const Tiling tiny_opts[] = {{0, 48, 6, 512}, {0, 32, 4, 256}, {1, 32, 1, 256}};
   static const Tiling small_opts[] = {{0, 56, 4, 512}, {0, 48, 3, 512}, {1, 32, 1, 256}};
   static const Tiling large_opts[] = {{3, 48, 2, 256}, {0, 48, 2, 512}, {1, 32, 1, 256}};
   static const Tiling tour_tiny[] = {{0, 48, 6, 512}, {0, 32, 4, 256}, {0, 32, 1, 256}};
-  static const Tiling tour_small[] = {{0, 48, 3, 512}, {0, 40, 3, 512}, {0, 32, 1, 256}};
-  static const Tiling tour_large[] = {{0, 48, 2, 512}, {0, 40, 2, 256}, {0, 32, 1, 256}};
+  static const Tiling tour_small[] = {{0, 52, 4, 512}, {0, 48, 3, 512}, {0, 32, 1, 256}};
+  static const Tiling tour_large[] = {{0, 56, 2, 512}, {0, 48, 2, 512}, {0, 32, 1, 256}};
   static const Tiling nb8_tiny[] = {{0, 48, 6, 512}, {0, 32, 4, 256}, {0, 32, 1, 256}};
   static const Tiling nb8_small[] = {{0, 56, 4, 512}, {0, 48, 3, 512}, {0, 32, 1, 256}};
   static const Tiling nb8_large[] = {{0, 56, 2, 512}, {0, 48, 2, 512}, {0, 32, 1, 256}};

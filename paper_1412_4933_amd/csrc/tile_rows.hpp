@@ -15,7 +15,9 @@
 // commit. Only agents that draw a choice (two or more empty side candidates)
 // or that may meet a contest need their Philox words; they are queued and
 // all waves draw them together, so a step has one Philox pass, and its word
-// 0 is kept as the agent's ticket for the resolution.
+// 0 is kept as the agent's ticket for the resolution (the streaming form and
+// the tour variant keep no tickets: only choices are queued, and a contested
+// cell draws its contenders' words again).
 //
 // Per step (B = workgroup barrier):
 //   1. masks     (wave 0) forward requests, single-candidate side requests,
@@ -73,7 +75,7 @@ struct RowsLayout {
   __host__ __device__ size_t ctl() const { return moved() + (size_t)R * 8; }             // 16 u32
   __host__ __device__ size_t ids() const { return ctl() + 64; }                         // [R][64] u32
   __host__ __device__ size_t tick() const { return ids() + (size_t)R * 256; }           // [R][64] u32
-  __host__ __device__ size_t queue() const { return tick() + (stream ? 0 : (size_t)R * 256); }  // [R*64] u16
+  __host__ __device__ size_t queue() const { return tick() + (stream || tour ? 0 : (size_t)R * 256); }  // [R*64] u16
   __host__ __device__ size_t tau() const { return queue() + (size_t)R * 128; }          // [2][R][64] f32
   __host__ __device__ size_t tour_len() const { return tau() + (aco && !stream ? (size_t)R * 512 : 0); }  // [R][64] f32
   __host__ __device__ size_t bytes() const { return tour_len() + (tour ? (size_t)R * 256 : 0); }
@@ -162,6 +164,10 @@ template <int MODE, bool STREAM = false, bool NB8 = false>
 __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k_max, int tx, int ty, int tile_index,
                                   uint64_t t0, int steps, bool last) {
   static_assert(!(NB8 && STREAM), "the eight-neighbour set runs on the LDS form only");
+  // Contest tickets are kept per cell from the draw, except in the streaming
+  // form and the tour variant, which give that LDS to other arrays and draw
+  // a contested cell's contenders again instead.
+  constexpr bool kTicks = !STREAM && MODE != 2;
   const RowsLayout L{R, k_max, MODE != 0, STREAM, MODE == 2, NB8};
   uint64_t* hist = (uint64_t*)(smem + L.hist());
   uint64_t* wall_m = (uint64_t*)(smem + L.wall());
@@ -285,8 +291,10 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
         pones |= P[q];
       }
       const uint64_t pu = from_up(twos), pd = from_down(twos);
-      const uint64_t need = (Pv0 & (twos >> 1)) | (Pv1 & (twos << 1)) | (Sq[2] & (pu >> 1)) | (Sq[3] & (pd >> 1)) |
-                            (Sq[4] & (pu << 1)) | (Sq[5] & (pd << 1)) | (Sq[6] & pu) | (Sq[7] & pd);
+      const uint64_t need =
+          kTicks ? ((Pv0 & (twos >> 1)) | (Pv1 & (twos << 1)) | (Sq[2] & (pu >> 1)) | (Sq[3] & (pd >> 1)) |
+                    (Sq[4] & (pu << 1)) | (Sq[5] & (pd << 1)) | (Sq[6] & pu) | (Sq[7] & pd))
+                 : 0ull;
       if (row_lane) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) side[q * R + lane] = 0ull;
@@ -327,7 +335,7 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
         ones |= P[q];
       }
       uint64_t need = 0ull;  // with recomputed tickets only the choices are queued
-      if (!STREAM) {
+      if (kTicks) {
         const uint64_t pu = from_up(twos), pd = from_down(twos);
         need = (fA & (twos >> 1)) | (fB & (twos << 1)) | (oA0 & (pu >> 1)) | (oA1 & (pd >> 1)) |
                (oB0 & (pu << 1)) | (oB1 & (pd << 1)) | (o2 & pu) | (o3 & pd);
@@ -369,7 +377,7 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
         const unsigned avail = (bf & (unsigned)(eu >> cfc)) | ((bf & (unsigned)(ed >> cfc)) << 1) |
                                (((unsigned)(eu >> c) & 1u) << 2) | (((unsigned)(ed >> c) & 1u) << 3);
         const Words w = agent_words(id - 1u, t, S.key0, S.key1);
-        if (!STREAM) tick[r * 64 + c] = w.w0;
+        if (kTicks) tick[r * 64 + c] = w.w0;
         if constexpr (NB8) {
           // backward column; candidates 4 B (r, cbc), 5 BD- (ru, cbc), 6 BD+ (rd, cbc)
           const int cb = c - d;
@@ -577,9 +585,9 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
             sr = sr < 0 ? 0 : (sr >= R ? R - 1 : sr);
             sc = sc < 0 ? 0 : (sc > 63 ? 63 : sc);
             kk[q] = ids[sr * 64 + sc];
-            if (!STREAM) tk[q] = tick[sr * 64 + sc];
+            if (kTicks) tk[q] = tick[sr * 64 + sc];
           }
-          if (STREAM) {  // the contenders' tickets, drawn again (independent chains)
+          if (!kTicks) {  // the contenders' tickets, drawn again (independent chains)
 #pragma unroll
             for (int q = 0; q < 8; ++q)
               tk[q] = ((dirs >> q) & 1u) ? agent_words(kk[q] - 1u, t, S.key0, S.key1).w0 : 0xFFFFFFFFu;
