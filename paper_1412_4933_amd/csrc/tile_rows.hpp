@@ -15,9 +15,9 @@
 // commit. Only agents that draw a choice (two or more empty side candidates)
 // or that may meet a contest need their Philox words; they are queued and
 // all waves draw them together, so a step has one Philox pass, and its word
-// 0 is kept as the agent's ticket for the resolution (the streaming form and
-// the tour variant keep no tickets: only choices are queued, and a contested
-// cell draws its contenders' words again).
+// 0 is kept as the agent's ticket for the resolution (the streaming form, the
+// tour variant and the eight-neighbour form keep no tickets: only choices are
+// queued, and a contested cell draws its contenders' words again).
 //
 // Per step (B = workgroup barrier):
 //   1. masks     (wave 0) forward requests, single-candidate side requests,
@@ -75,7 +75,7 @@ struct RowsLayout {
   __host__ __device__ size_t ctl() const { return moved() + (size_t)R * 8; }             // 16 u32
   __host__ __device__ size_t ids() const { return ctl() + 64; }                         // [R][64] u32
   __host__ __device__ size_t tick() const { return ids() + (size_t)R * 256; }           // [R][64] u32
-  __host__ __device__ size_t queue() const { return tick() + (stream || tour ? 0 : (size_t)R * 256); }  // [R*64] u16
+  __host__ __device__ size_t queue() const { return tick() + (stream || tour || nb8 ? 0 : (size_t)R * 256); }  // [R*64] u16
   __host__ __device__ size_t tau() const { return queue() + (size_t)R * 128; }          // [2][R][64] f32
   __host__ __device__ size_t tour_len() const { return tau() + (aco && !stream ? (size_t)R * 512 : 0); }  // [R][64] f32
   __host__ __device__ size_t bytes() const { return tour_len() + (tour ? (size_t)R * 256 : 0); }
@@ -165,9 +165,11 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
                                   uint64_t t0, int steps, bool last) {
   static_assert(!(NB8 && STREAM), "the eight-neighbour set runs on the LDS form only");
   // Contest tickets are kept per cell from the draw, except in the streaming
-  // form and the tour variant, which give that LDS to other arrays and draw
-  // a contested cell's contenders again instead.
-  constexpr bool kTicks = !STREAM && MODE != 2;
+  // form, the tour variant and the eight-neighbour form, which draw a
+  // contested cell's contenders again instead: that queues only the agents
+  // that choose (with backward cells open, far more agents could meet a
+  // contest than end up in one) and frees the LDS of the tickets.
+  constexpr bool kTicks = !STREAM && MODE != 2 && !NB8;
   const RowsLayout L{R, k_max, MODE != 0, STREAM, MODE == 2, NB8};
   uint64_t* hist = (uint64_t*)(smem + L.hist());
   uint64_t* wall_m = (uint64_t*)(smem + L.wall());
