@@ -170,7 +170,7 @@ int sim_read_state(sim_handle* h, uint8_t* code, uint32_t* id, float* tau, void*
 
 /*
  * Tiling of the step kernel for `mode` (SIM_MODE_*; results never depend on
- * it; the tour variant accepts nw = 0 only): each
+ * it; the tour variant and the eight-neighbour set accept nw = 0 only): each
  * workgroup of `threads` lanes (multiple of 64, <= 1024) stages a region of
  * `rows` rows in LDS and advances it `steps_per_launch` steps per launch; the
  * tile interior is the region minus 3*steps_per_launch cells on every side
