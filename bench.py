@@ -200,6 +200,27 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes_per_dispatch": n * 4, "dispatches": 4}), flush=True)
 
 
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 8) -> float:
+    """Achievable HBM bandwidth on this machine: a plain device-to-device copy of
+    nbytes (read nbytes + write nbytes per copy), best of `reps`, in GB/s."""
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        b.copy_(a)
+        e.record()
+        torch.cuda.synchronize()
+        best = min(best, s.elapsed_time(e) / 1e3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * n * 4 / best / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,6 +338,9 @@ def main():
                                                "launches": v[1]} for k, v in per_kernel.items()}}
     if traffic is not None:
         roofline["traffic_gbs"] = round(traffic / (dom_avg_ms / 1e3) / 1e9, 1)
+        roofline["traffic_frac"] = round(roofline["traffic_gbs"] / HBM_PEAK_GBS, 4)
+    # the achievable bandwidth of a plain copy on this machine, beside the published peak
+    roofline["copy_gbs"] = round(copy_bandwidth(), 1)
 
 
     cpu = None
