@@ -198,7 +198,9 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
   // which also land in wave 0) are the serial part of every step: let it
   // win instruction arbitration over the throughput phases of a workgroup
   // sharing its compute unit (measured: 1024x512 ACO 7.18 -> 6.95 us/step).
-  if (mask_wave) __builtin_amdgcn_s_setprio(2);
+  // The streaming form, four or five workgroups to a compute unit, loses
+  // from it (256-scenario batch 8.5e9 -> 8.3e9 agent-steps/s).
+  if (!STREAM && mask_wave) __builtin_amdgcn_s_setprio(2);
   const int h = S.halo;
   const int x0 = tx * S.IX - h;  // region origin in grid coordinates
   const int y0 = ty * S.IY - h;
