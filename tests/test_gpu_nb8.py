@@ -154,3 +154,12 @@ def test_nb8_errors(pedsim):
     assert e.value.code == pedsim.SIM_EINVAL
     assert sim.tiling(S.MODE_ACO)[0] == 0
     sim.close()
+
+
+@pytest.mark.parametrize("mode", [S.MODE_ACO, S.MODE_ACO_TOUR])
+def test_nb8_1024x512_default_tiling(pedsim, mode):
+    """The benchmark's eight-neighbour workload in its launch configuration."""
+    scn = S.aco_nb8_1024x512()
+    scn.mode = mode
+    say("nb8 1024x512", mode)
+    run_both(pedsim, scn, mode, 200, chunks=(1, 7, 40))
