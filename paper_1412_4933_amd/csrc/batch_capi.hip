@@ -97,7 +97,7 @@ namespace {
 // The eight-neighbour set runs on the row-lane engine with the pheromone in
 // LDS: two 512-thread workgroups per compute unit.
 Tiling default_batch_tiling(bool lds_form = false) {
-  static const Tiling opts[] = {{3, 56, 3, 256}, {0, 48, 3, 512}, {1, 32, 1, 256}};
+  static const Tiling opts[] = {{3, 62, 3, 256}, {3, 56, 3, 256}, {1, 32, 1, 256}};
   static const Tiling opts8[] = {{0, 48, 3, 512}, {0, 40, 2, 512}, {0, 32, 1, 256}};
   const Tiling* o = lds_form ? opts8 : opts;
   for (int i = 0; i < 3; ++i)
@@ -235,7 +235,7 @@ int sim_batch_create(int32_t capacity, void* d_workspace, size_t workspace_bytes
   b->staging = nullptr;
   b->upload_pending = false;
   b->tl = default_batch_tiling();
-  b->wgs_per_cu = 4;  // the default streaming tiling needs ~36 KB of LDS: four workgroups fit a CU
+  b->wgs_per_cu = 4;  // the default streaming tiling needs ~40 KB of LDS: four workgroups fit a CU
   b->use_graph = 1;
   b->nb8 = false;
   b->tour = false;
