@@ -231,9 +231,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--autotune", action="store_true", help="autotune the batch launch shape first")
     ap.add_argument("--requests", type=int, default=512, help="requests in the served run")
-    ap.add_argument("--rate", type=float, default=510.0,
+    ap.add_argument("--rate", type=float, default=540.0,
                     help="request arrival rate (1/s); default 0.8 x the batched throughput "
-                         "(8.6e9 agent-steps/s) over the mean request work (13.4M agent-steps)")
+                         "(9.1e9 agent-steps/s) over the mean request work (13.4M agent-steps)")
     ap.add_argument("--budget-gib", type=float, default=2.0, help="HBM budget for resident scenarios")
     ap.add_argument("--quantum", type=int, default=100, help="steps per serving quantum")
     ap.add_argument("--no-serve", action="store_true", help="skip the served run of the default line")
