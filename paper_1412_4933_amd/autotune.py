@@ -24,14 +24,16 @@ PLAIN_CANDIDATES = [
     (1, 32, 1, 256), (1, 32, 2, 512), (1, 48, 2, 512), (1, 64, 2, 512), (1, 64, 3, 512),
     (1, 96, 2, 1024), (1, 128, 3, 1024), (2, 32, 2, 512), (2, 64, 2, 1024), (2, 64, 3, 1024),
     (0, 64, 2, 256), (0, 64, 3, 256), (0, 64, 4, 256), (0, 48, 2, 256), (0, 64, 3, 512),
-    (0, 56, 4, 512), (0, 48, 6, 512), (3, 48, 2, 256), (3, 48, 3, 256), (3, 64, 2, 256),
+    (0, 56, 4, 512), (0, 52, 4, 512), (0, 48, 6, 512), (3, 48, 2, 256), (3, 48, 3, 256),
+    (3, 64, 2, 256), (3, 50, 2, 256),
 ]
 # (nw, rows, steps per launch, threads, workgroups per CU)
 BATCH_CANDIDATES = [
     (1, 32, 1, 256, 4), (1, 32, 2, 512, 2), (1, 32, 2, 512, 4), (1, 48, 2, 512, 2), (1, 64, 2, 512, 2),
     (1, 64, 3, 512, 2), (1, 64, 2, 1024, 1), (1, 96, 3, 1024, 1), (2, 48, 2, 1024, 1),
     (0, 64, 2, 256, 2), (0, 64, 3, 256, 2), (0, 48, 2, 256, 3), (0, 64, 2, 128, 4),
-    (0, 48, 3, 512, 2), (3, 48, 2, 256, 4), (3, 48, 3, 256, 4),
+    (0, 48, 3, 512, 2), (3, 48, 2, 256, 4), (3, 48, 3, 256, 4), (3, 56, 3, 256, 4), (3, 60, 3, 256, 4),
+    (3, 62, 3, 256, 4),
 ]
 
 _cache: Dict[str, tuple] = {}
