@@ -197,10 +197,17 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
   // The mask wave's phases (and the draws and contests of small queues,
   // which also land in wave 0) are the serial part of every step: let it
   // win instruction arbitration over the throughput phases of a workgroup
-  // sharing its compute unit (measured: 1024x512 ACO 7.18 -> 6.95 us/step).
-  // The streaming form, four or five workgroups to a compute unit, loses
-  // from it (256-scenario batch 8.5e9 -> 8.3e9 agent-steps/s).
-  if (!STREAM && mask_wave) __builtin_amdgcn_s_setprio(2);
+  // sharing its compute unit, and let every wave's step work go before
+  // such a workgroup's write-back, which drops back to the base priority
+  // (measured: 1024x512 ACO 7.18 -> 6.82 us/step, eight neighbours
+  // 9.92 -> 9.53). The streaming form, four or five workgroups to a compute
+  // unit, loses from it (256-scenario batch 8.5e9 -> 8.3e9 agent-steps/s).
+  if (!STREAM) {
+    if (mask_wave)
+      __builtin_amdgcn_s_setprio(2);
+    else
+      __builtin_amdgcn_s_setprio(1);
+  }
   const int h = S.halo;
   const int x0 = tx * S.IX - h;  // region origin in grid coordinates
   const int y0 = ty * S.IY - h;
@@ -681,6 +688,8 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
   }
   if (mask_wave && row_lane) moved_m[lane] = moved_in;
   __syncthreads();
+
+  if (!STREAM) __builtin_amdgcn_s_setprio(0);
 
   // ---- write the interior back; pheromone applied step by step ------------
   // Interior rows are dealt round-robin to the waves, kWriteRows at a time;
