@@ -2,8 +2,13 @@
 
 TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
 CPU-baseline leg may use this package; the library never does. It builds the
-oracle with gcc (-O2 -ffp-contract=off, plain loops, one thread) on first use
-if the shared object is missing, and `build()` rebuilds it unconditionally.
+oracle with gcc (-O2 -ffp-contract=off, plain loops) on first use if a shared
+object is missing, and `build()` rebuilds both unconditionally:
+  libpedsim_oracle.so      the plain build, one thread;
+  libpedsim_oracle_omp.so  the same source with -fopenmp, whose parallel loops
+                           write disjoint cells, so its results are identical.
+`State(..., threads=n)` runs on the OpenMP build with n threads; the default
+(threads=None) is the plain build.
 """
 from __future__ import annotations
 
@@ -17,6 +22,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pedsim_oracle.c")
 _LIB = os.path.join(_HERE, "libpedsim_oracle.so")
+_LIB_OMP = os.path.join(_HERE, "libpedsim_oracle_omp.so")
 # The mutation tests point this at a deliberately broken build of the oracle.
 _LIB_OVERRIDE = os.environ.get("PEDSIM_ORACLE_LIB")
 
@@ -33,24 +39,42 @@ class OracleParams(ctypes.Structure):
     ]
 
 
+_FLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def _compile(out: str, extra) -> str:
+    tmp = out + ".tmp"
+    subprocess.run(["gcc", *_FLAGS, *extra, "-o", tmp, _SRC, "-lm"], check=True)
+    os.replace(tmp, out)
+    return out
+
+
 def build() -> str:
-    """Compile the oracle into oracle/libpedsim_oracle.so."""
-    tmp = _LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-           "-shared", "-o", tmp, _SRC, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB)
-    return _LIB
+    """Compile the oracle into oracle/libpedsim_oracle.so (one thread) and
+    oracle/libpedsim_oracle_omp.so (OpenMP)."""
+    _compile(_LIB_OMP, ["-fopenmp"])
+    return _compile(_LIB, [])
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        path = _LIB_OVERRIDE or _LIB
-        if not _LIB_OVERRIDE and not os.path.exists(_LIB):
+def cpu_threads() -> int:
+    """Host threads this process may use (its CPU affinity), at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def lib(parallel: bool = False):
+    """The plain oracle build, or with parallel=True the OpenMP build."""
+    L = _libs.get(parallel)
+    if L is None:
+        target = _LIB_OMP if parallel else _LIB
+        path = _LIB_OVERRIDE or target
+        if not _LIB_OVERRIDE and not os.path.exists(target):
             build()
         L = ctypes.CDLL(path)
         P = ctypes.POINTER
@@ -76,8 +100,10 @@ def lib():
                                       ctypes.c_void_p, ctypes.c_void_p]
         L.oracle_run_tour.restype = ctypes.c_int64
         L.oracle_counts.argtypes = [P(OracleParams), ctypes.c_void_p, P(ctypes.c_uint64)]
-        _lib = L
-    return _lib
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = ctypes.c_int
+        _libs[parallel] = L
+    return L
 
 
 def philox4x32_10(ctr, key) -> Tuple[int, int, int, int]:
@@ -112,11 +138,14 @@ class State:
     """Host copy of one scenario's planes, advanced by the oracle.
 
     `tour` is the tour matrix of the tour variant (one float per agent,
-    index = agent number = id - 1); zeros when not given."""
+    index = agent number = id - 1); zeros when not given. `threads` (an int)
+    runs every call on the OpenMP build with that many threads; None runs the
+    plain one-thread build."""
 
     def __init__(self, code, ids, tau=None, *, seed: int, rho: float = 0.1,
                  dtau: float = 1.0, alpha: int = 1, beta: int = 2, cross_a: int = 1,
-                 cross_b: int = 1, t: int = 0, tour=None, neighbours: int = 5):
+                 cross_b: int = 1, t: int = 0, tour=None, neighbours: int = 5,
+                 threads: Optional[int] = None):
         self.code = np.ascontiguousarray(code, dtype=np.uint8).copy()
         self.ids = np.ascontiguousarray(ids, dtype=np.uint32).copy()
         self.H, self.W = self.code.shape
@@ -134,12 +163,23 @@ class State:
         self.p = OracleParams(self.W, self.H, seed, rho, dtau, alpha, beta, cross_a,
                               cross_b, neighbours)
         self.t = t
+        self.threads = threads
 
     @classmethod
-    def from_scenario(cls, s) -> "State":
+    def from_scenario(cls, s, threads: Optional[int] = None) -> "State":
         return cls(s.code, s.ids, s.tau, seed=s.seed, rho=s.rho, dtau=s.dtau,
                    alpha=s.alpha, beta=s.beta, cross_a=s.cross_a, cross_b=s.cross_b,
-                   tour=getattr(s, "tour", None), neighbours=getattr(s, "neighbours", 5))
+                   tour=getattr(s, "tour", None), neighbours=getattr(s, "neighbours", 5),
+                   threads=threads)
+
+    def _lib(self):
+        """The build this state runs on; the OpenMP build's thread count is a
+        per-calling-thread setting, so it is set before every call."""
+        if self.threads is None:
+            return lib()
+        L = lib(parallel=True)
+        L.oracle_set_threads(int(self.threads))
+        return L
 
     def _tau_ptrs(self, mode):
         if mode in (MODE_ACO, MODE_ACO_TOUR):
@@ -158,12 +198,12 @@ class State:
         rq = None if req is None else req.ctypes.data
         wn = None if win is None else win.ctypes.data
         if mode == MODE_ACO_TOUR:
-            moved = lib().oracle_step_tour(ctypes.byref(self.p), self.t, self.code.ctypes.data,
+            moved = self._lib().oracle_step_tour(ctypes.byref(self.p), self.t, self.code.ctypes.data,
                                            self.ids.ctypes.data, ta, tb,
                                            self.tour.ctypes.data if self.tour.size else None,
                                            rq, wn)
         else:
-            moved = lib().oracle_step(ctypes.byref(self.p), mode, self.t, self.code.ctypes.data,
+            moved = self._lib().oracle_step(ctypes.byref(self.p), mode, self.t, self.code.ctypes.data,
                                       self.ids.ctypes.data, ta, tb, rq, wn)
         if moved < 0:
             raise MemoryError("oracle step failed to allocate")
@@ -173,11 +213,11 @@ class State:
     def run(self, mode: int, nsteps: int) -> int:
         ta, tb = self._tau_ptrs(mode)
         if mode == MODE_ACO_TOUR:
-            moved = lib().oracle_run_tour(ctypes.byref(self.p), self.t, nsteps,
+            moved = self._lib().oracle_run_tour(ctypes.byref(self.p), self.t, nsteps,
                                           self.code.ctypes.data, self.ids.ctypes.data, ta, tb,
                                           self.tour.ctypes.data if self.tour.size else None)
         else:
-            moved = lib().oracle_run(ctypes.byref(self.p), mode, self.t, nsteps,
+            moved = self._lib().oracle_run(ctypes.byref(self.p), mode, self.t, nsteps,
                                      self.code.ctypes.data, self.ids.ctypes.data, ta, tb)
         if moved < 0:
             raise MemoryError("oracle step failed to allocate")
@@ -187,5 +227,5 @@ class State:
     def counts(self):
         """(agents_a, agents_b, crossed_a, crossed_b)."""
         o = (ctypes.c_uint64 * 4)()
-        lib().oracle_counts(ctypes.byref(self.p), self.code.ctypes.data, o)
+        self._lib().oracle_counts(ctypes.byref(self.p), self.code.ctypes.data, o)
         return tuple(int(v) for v in o)

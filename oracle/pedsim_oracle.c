@@ -65,12 +65,24 @@
  * All float arithmetic is IEEE binary32, one operation at a time, without
  * contraction into fused multiply-adds (built with -ffp-contract=off) and
  * with subnormals kept.
+ *
+ * Threads: the same source builds twice, plainly (one thread; the OpenMP
+ * pragmas are ignored) and with -fopenmp. Every parallel loop below runs over
+ * cells whose iterations write disjoint entries: a request is written only at
+ * its agent's cell; a cell that is empty at t is the only one that writes
+ * itself and the source cell of its winner (a source is never empty at t and
+ * is won by at most one cell, since its agent made one request); the
+ * pheromone update and the counts touch one cell each. Integer sums are
+ * exact in any order. So both builds give identical results.
  */
 #include <stddef.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define O_EMPTY 0
 #define O_A 1
@@ -336,6 +348,7 @@ static int64_t step_any(const oracle_params *p, int32_t mode, uint64_t t, uint8_
   if (win_out) memset(win_out, 0, cells);
 
   /* 1. request, every agent on the snapshot of time t */
+#pragma omp parallel for private(x) schedule(static)
   for (y = 0; y < H; ++y)
     for (x = 0; x < W; ++x) {
       size_t c = (size_t)y * W + x;
@@ -346,6 +359,7 @@ static int64_t step_any(const oracle_params *p, int32_t mode, uint64_t t, uint8_
   /* 2.+3. resolve every cell empty at t, then commit into fresh planes */
   memcpy(new_code, code, cells);
   memcpy(new_id, id, cells * sizeof(uint32_t));
+#pragma omp parallel for private(x) reduction(+ : moved) schedule(static)
   for (y = 0; y < H; ++y)
     for (x = 0; x < W; ++x) {
       size_t c = (size_t)y * W + x;
@@ -400,6 +414,7 @@ static int64_t step_any(const oracle_params *p, int32_t mode, uint64_t t, uint8_
     float rho = p->rho;
     float keep = 1.0f - rho;
     size_t c;
+#pragma omp parallel for schedule(static)
     for (c = 0; c < cells; ++c) {
       float va = keep * tau_a[c];
       float vb = keep * tau_b[c];
@@ -415,6 +430,7 @@ static int64_t step_any(const oracle_params *p, int32_t mode, uint64_t t, uint8_
     float rho = p->rho;
     float keep = 1.0f - rho;
     size_t c;
+#pragma omp parallel for schedule(static)
     for (c = 0; c < cells; ++c) {
       float evaporated_a = keep * tau_a[c];
       float evaporated_b = keep * tau_b[c];
@@ -450,18 +466,35 @@ int64_t oracle_step_tour(const oracle_params *p, uint64_t t, uint8_t *code, uint
  * out[3] B at x < cross_a. */
 void oracle_counts(const oracle_params *p, const uint8_t *code, uint64_t out[4]) {
   int x, y;
-  memset(out, 0, 4 * sizeof(uint64_t));
+  uint64_t n_a = 0, n_b = 0, crossed_a = 0, crossed_b = 0;
+#pragma omp parallel for private(x) reduction(+ : n_a, n_b, crossed_a, crossed_b) schedule(static)
   for (y = 0; y < p->H; ++y)
     for (x = 0; x < p->W; ++x) {
       int g = code[(size_t)y * p->W + x];
       if (g == O_A) {
-        out[0] += 1;
-        if (x >= p->W - p->cross_b) out[2] += 1;
+        n_a += 1;
+        if (x >= p->W - p->cross_b) crossed_a += 1;
       } else if (g == O_B) {
-        out[1] += 1;
-        if (x < p->cross_a) out[3] += 1;
+        n_b += 1;
+        if (x < p->cross_a) crossed_b += 1;
       }
     }
+  out[0] = n_a;
+  out[1] = n_b;
+  out[2] = crossed_a;
+  out[3] = crossed_b;
+}
+
+/* Threads the OpenMP build uses from now on (n >= 1); returns the number it
+ * will use, 1 in the plain build. */
+int oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }
 
 /* nsteps steps from step t0; returns the moves of the last step (or -1). */

@@ -54,6 +54,14 @@ MUTANTS = {
                                  "eta[4] = heuristic_weight(D2_BACK_DIAGONAL, p->beta);"),
     "nb8_back_pair_order_fixed": ("O_REQ_B, O_REQ_BDP, O_REQ_BDM};", "O_REQ_B, O_REQ_BDM, O_REQ_BDP};"),
     "nb8_three_thresholds_only": ("for (i = 0; i < sides - 1; ++i)", "for (i = 0; i < 3; ++i)"),
+    "crossing_edge_strict": ("if (x >= p->W - p->cross_b) crossed_a += 1;",
+                             "if (x > p->W - p->cross_b) crossed_a += 1;"),
+    "crossing_bands_swapped": ("if (x >= p->W - p->cross_b) crossed_a += 1;",
+                               "if (x >= p->W - p->cross_a) crossed_a += 1;"),
+    "crossing_b_edge_inclusive": ("if (x < p->cross_a) crossed_b += 1;",
+                                  "if (x <= p->cross_a) crossed_b += 1;"),
+    "crossing_b_band_swapped": ("if (x < p->cross_a) crossed_b += 1;",
+                                "if (x < p->cross_b) crossed_b += 1;"),
 }
 
 

@@ -265,6 +265,73 @@ def test_lone_agent_crosses_in_w_minus_1_steps(mode, group):
 
 
 # ----------------------------------------------------------------------------
+# Crossing counts (Sec. VI): an agent has crossed once it stands inside the
+# opposite group's starting band, i.e. in one of the last cross_b columns for
+# A (B starts there) or one of the first cross_a columns for B.
+# ----------------------------------------------------------------------------
+
+def test_crossing_count_band_edges():
+    """Agents placed on both sides of each band edge, with bands of unequal
+    width so that a swapped band or an off-by-one edge shows."""
+    W, H, cross_a, cross_b = 30, 8, 3, 7
+    code = S.wall_frame(W, H)
+    # A: band of B = columns W-7 .. W-1 = 23 .. 29
+    code[1, W - cross_b - 1] = S.GROUP_A   # x = 22: outside B's band
+    code[2, W - cross_b] = S.GROUP_A       # x = 23: first column of B's band
+    code[3, W - 1] = S.GROUP_A             # x = 29: last column
+    code[4, W - cross_a] = S.GROUP_A       # x = 27: inside B's band (inside A's width too)
+    code[5, W - cross_a - 1] = S.GROUP_A   # x = 26: inside B's band, not A's width
+    # B: band of A = columns 0 .. 2
+    code[1, cross_a] = S.GROUP_B           # x = 3: outside A's band
+    code[2, cross_a - 1] = S.GROUP_B       # x = 2: last column of A's band
+    code[3, 0] = S.GROUP_B                 # x = 0
+    code[4, cross_b - 1] = S.GROUP_B       # x = 6: would count if the bands were swapped
+    code[6, 10] = S.GROUP_B                # far from both bands
+    st = oracle.State.from_scenario(S.from_grid(code, band_a=cross_a, band_b=cross_b))
+    assert (st.p.cross_a, st.p.cross_b) == (cross_a, cross_b)
+    n_a, n_b, crossed_a, crossed_b = st.counts()
+    assert (n_a, n_b) == (5, 5)
+    assert crossed_a == 4   # x = 23, 29, 27, 26
+    assert crossed_b == 2   # x = 2, 0
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_LEM, oracle.MODE_ACO])
+def test_crossing_count_of_a_lone_walk(mode):
+    """A lone agent of each group walks straight along its own row (forward
+    first, nothing in the way): after t steps A stands at x = t and B at
+    x = W-1-t, so A counts as crossed from step W - cross_b on (when it enters
+    the first column of B's band) and B from step W - cross_a on."""
+    W, H, cross_a, cross_b = 25, 5, 4, 9
+    code = S.wall_frame(W, H)
+    code[1, 0] = S.GROUP_A
+    code[3, W - 1] = S.GROUP_B
+    st = oracle.State.from_scenario(S.from_grid(code, band_a=cross_a, band_b=cross_b,
+                                                tau=np.ones((2, H, W), np.float32)))
+    for t in range(0, W):
+        if t:
+            st.step(mode)
+        assert st.code[1, t] == S.GROUP_A and st.code[3, W - 1 - t] == S.GROUP_B
+        _, _, crossed_a, crossed_b = st.counts()
+        assert crossed_a == (1 if t >= W - cross_b else 0), t
+        assert crossed_b == (1 if t >= W - cross_a else 0), t
+
+
+def test_crossing_count_of_seeded_bands():
+    """In a fresh scenario nobody has crossed (each group fills only its own
+    band); a group moved as a block into the opposite band counts in full."""
+    scn = S.make_scenario(120, 30, 300, 250, band_a=9, band_b=13, seed=5, mode=S.MODE_LEM)
+    st = oracle.State.from_scenario(scn)
+    assert st.counts() == (300, 250, 0, 0)
+    code = S.wall_frame(scn.W, scn.H)
+    code[1:scn.H - 1, :scn.band_a] = S.GROUP_B      # every B inside A's band
+    code[1:scn.H - 1, scn.W - scn.band_b:] = S.GROUP_A  # every A inside B's band
+    moved = oracle.State.from_scenario(S.from_grid(code, band_a=scn.band_a, band_b=scn.band_b))
+    n_b = (scn.H - 2) * scn.band_a
+    n_a = (scn.H - 2) * scn.band_b
+    assert moved.counts() == (n_a, n_b, n_a, n_b)
+
+
+# ----------------------------------------------------------------------------
 # Invariants on seeded crowds
 # ----------------------------------------------------------------------------
 
