@@ -87,56 +87,91 @@ def measured_traffic(workload: str, kernel: str, tiling=None):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(workload: str, budget_s: float):
+def _oracle_leg(scn, mode, threads, budget_s):
+    """Time the oracle on a sample of roughly budget_s seconds: steps
+    5..5+n of the workload (the first 5 size the sample)."""
     import oracle
-    scn = make(workload)
-    st = oracle.State.from_scenario(scn)
-    # size the sample to roughly budget_s of single-thread work
+    st = oracle.State.from_scenario(scn, threads=threads)
     t0 = time.perf_counter()
-    st.run(scn.mode, 5)
+    st.run(mode, 5)
     per = (time.perf_counter() - t0) / 5
     n = max(5, min(scn.steps - 5, int(budget_s / max(per, 1e-6))))
     t0 = time.perf_counter()
-    st.run(scn.mode, n)
+    st.run(mode, n)
     dt = time.perf_counter() - t0
-    return {"value": scn.agents * n / dt, "unit": "agent-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"steps 5..{5 + n} of the {WORKLOADS[workload][1]} workload, "
-                      f"plain C oracle, one thread, {dt:.1f} s"}
+    return scn.agents * n / dt, n, dt
 
 
-def run_batched(args):
-    """All 256 scenarios advanced together vs the same scenarios one after
-    another through the plain path; K steps each."""
+def cpu_baseline(workload: str, budget_s: float):
+    """The oracle as it stands, on this host: the plain build on one thread
+    (the paper's CPU baseline is one thread) and the OpenMP build of the same
+    source on all the cores this process may use (at most 16), each on a
+    bounded sample of the workload. `value` and `cores` are the all-core
+    leg's."""
+    import oracle
+    scn = make(workload)
+    mode = 1 if workload == "stress_aco_4096x2048" else scn.mode
+    threads = oracle.cpu_threads()
+    v1, n1, dt1 = _oracle_leg(scn, mode, None, budget_s)
+    vn, nn, dtn = _oracle_leg(scn, mode, threads, budget_s)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {"value": vn, "unit": "agent-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"steps 5..{5 + nn} of the {WORKLOADS[workload][1]} workload, "
+                      f"C oracle (OpenMP build), {threads} threads, {dtn:.1f} s",
+            "one_thread": {"value": v1, "cores": 1,
+                           "sample": f"steps 5..{5 + n1}, C oracle (plain build), one thread, "
+                                     f"{dt1:.1f} s"},
+            "nproc": os.cpu_count(), "affinity_cpus": affinity}
+
+
+def batched_run(K: int, warmup: int, autotune_first: bool = False) -> dict:
+    """All 256 scenarios advanced together (one batch, captured launch
+    sequences) vs the same scenarios one after another through the plain
+    path; K steps each from the initial state. The batch first runs the same
+    K-step call untimed (it instantiates that call's graphs and applies the
+    autotuner's cached tuning), then every slot is refilled with the initial
+    state and the call is timed."""
     import torch
     from paper_1412_4933_amd import autotune, pedsim, scenarios
-    K = args.steps if args.steps is not None else 1000
     scns = scenarios.batched_256(steps=K)
     agents = sum(s.agents for s in scns)
-    tuning = None
-    if args.autotune:
+    if autotune_first:
         log("autotuning the batch ...")
-        tuning, timings = autotune.tune_batch(scns, steps=20)
+        best, timings = autotune.tune_batch(scns, steps=min(K, 200))
         log("autotune:", [(round(t * 1e3, 2), tu) for t, tu in timings[:5]])
+    initial = [pedsim._Resident(sc, "cuda") for sc in scns]  # one upload
     batch = pedsim.Batch(len(scns))
-    if tuning is not None:
-        batch.set_tuning(*tuning, 1)
-    for sc in scns:
-        batch.add(sc)
-    log(f"batch of {len(scns)} scenarios, {agents} agents, tuning {batch.tuning()}")
-    batch.step(args.warmup)  # also instantiates the captured launch sequences
+    for res in initial:
+        batch.add_resident(res.clone())
+    batch.step(K)
+    torch.cuda.synchronize()
+    for slot in list(batch.members):
+        batch.remove(slot)
+    for res in initial:
+        batch.add_resident(res.clone())
+    log(f"batch of {len(scns)} scenarios, {agents} agents")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     batch.step(K)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    tuning, source = batch.tuning(), batch.tuning_source
     batch.close()
+    del initial
     value = agents * K / wall
-    log(f"batched: {K} steps in {wall * 1e3:.1f} ms -> {value:.4g} agent-steps/s")
+    log(f"batched: {K} steps in {wall * 1e3:.1f} ms -> {value:.4g} agent-steps/s, "
+        f"tuning {tuning} ({source})")
     # back-to-back plain launches of the same scenarios (step calls only)
     plain = 0.0
     for sc in scns:
+        if warmup > 0:  # a throwaway run loads the scenario's kernel variant
+            sim = pedsim.Sim(sc)
+            sim.step(min(warmup, 4), sc.mode)
+            sim.close()
         sim = pedsim.Sim(sc)
-        sim.step(args.warmup, sc.mode)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         sim.step(K, sc.mode)
@@ -144,21 +179,26 @@ def run_batched(args):
         plain += time.perf_counter() - t1
         sim.close()
     log(f"back-to-back plain: {plain * 1e3:.1f} ms -> {agents * K / plain:.4g} agent-steps/s")
+    return {"scenarios": len(scns), "agents": agents, "steps": K, "wall_s": wall,
+            "agent_steps_per_s": value, "tuning": list(tuning), "tuning_source": source,
+            "back_to_back_plain": {"agent_steps_per_s": agents * K / plain, "wall_s": plain},
+            "speedup_vs_back_to_back": plain / wall}
+
+
+def run_batched(args):
+    K = args.steps if args.steps is not None else 1000
+    b = batched_run(K, args.warmup, args.autotune)
     line = {
-        "metric": "agent-steps/s (batched, 256 scenarios)", "value": value, "unit": "agent-steps/s",
-        "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": wall * 1e3 / K,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+u32",
-        "data": "synthetic",
-        "config": {"workload": WORKLOADS["batched_256"][1], "scenarios": len(scns), "agents": agents,
-                   "tuning": list(batch_tuning_or(tuning))},
-        "back_to_back_plain": {"value": agents * K / plain, "wall_s": plain},
-        "speedup_vs_back_to_back": plain / wall,
+        "metric": "agent-steps/s (batched, 256 scenarios)", "value": b["agent_steps_per_s"],
+        "unit": "agent-steps/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": b["wall_s"] * 1e3 / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+u32", "data": "synthetic",
+        "config": {"workload": WORKLOADS["batched_256"][1], "scenarios": b["scenarios"],
+                   "agents": b["agents"], "tuning": b["tuning"], "tuning_source": b["tuning_source"]},
+        "back_to_back_plain": b["back_to_back_plain"],
+        "speedup_vs_back_to_back": b["speedup_vs_back_to_back"],
     }
     print(json.dumps(line), flush=True)
-
-
-def batch_tuning_or(tuning):
-    return tuning if tuning is not None else ("default",)
 
 
 def served_run(n_requests: int, rate: float, budget: int, quantum: int, seed: int = 1):
@@ -237,6 +277,9 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=2.0, help="HBM budget for resident scenarios")
     ap.add_argument("--quantum", type=int, default=100, help="steps per serving quantum")
     ap.add_argument("--no-serve", action="store_true", help="skip the served run of the default line")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched run of the default line")
+    ap.add_argument("--batched-steps", type=int, default=1000,
+                    help="steps of the default line's batched run (the batched workload's own)")
     ap.add_argument("--tiling", default=None,
                     help="nw,rows,steps_per_launch,threads for the step kernel (default: the library's)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -269,6 +312,11 @@ def main():
         log(f"served run: {args.requests} requests at {args.rate}/s ...")
         served = served_run(args.requests, args.rate, int(args.budget_gib * (1 << 30)), args.quantum)
         log("served:", served)
+
+    batched = None
+    if not args.no_batched and args.workload == "aco_1024x512":
+        log(f"batched run: 256 scenarios x {args.batched_steps} steps ...")
+        batched = batched_run(args.batched_steps, min(args.warmup, 20))
 
     scn = make(args.workload)
     mode = scn.mode if args.workload != "stress_aco_4096x2048" else 1
@@ -309,9 +357,28 @@ def main():
     value = agents * K / sec
     log(f"timed {K} steps: {ms:.3f} ms (wall {wall * 1e3:.3f} ms), stats {stats}")
 
+    # the whole workload (all its steps from the initial state), beside the
+    # K timed steps of the line
+    full = None
+    if K != scn.steps and scn.steps:
+        fs = make_sim()
+        torch.cuda.synchronize(dev)
+        fa, fb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fa.record(stream)
+        fs.step(scn.steps, mode)
+        fb.record(stream)
+        torch.cuda.synchronize(dev)
+        fms = fa.elapsed_time(fb)
+        fs.close()
+        full = {"steps": scn.steps, "ms": fms, "ms_per_step": fms / scn.steps,
+                "agent_steps_per_s": agents * scn.steps / (fms / 1e3)}
+        log(f"full run: {scn.steps} steps in {fms:.3f} ms -> {full['agent_steps_per_s']:.4g} agent-steps/s")
+
     # per-launch durations of the step kernel with HIP events on the launch stream
     prof = make_sim()
     tiling = pedsim.sim_get_tiling(prof.h, mode)
+    tiling_source = ("--tiling" if tiling_arg is not None
+                     else "autotuner cache" if mode in prof.tuned else "library default")
     per_kernel = pedsim.sim_step_timed(prof.h, mode, K, stream)
     prof.close()
     log("tiling (nw, rows, steps/launch, threads):", tiling)
@@ -358,9 +425,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload][1], "grid": f"{scn.W}x{scn.H}",
                    "agents": agents, "mode": MODE_NAMES[mode], "seed": scn.seed,
-                   "neighbours": getattr(scn, "neighbours", 5)},
+                   "neighbours": getattr(scn, "neighbours", 5),
+                   "timed_steps": f"steps 0..{K - 1} of the workload's {scn.steps}, from its initial state",
+                   "tiling": list(tiling), "tiling_source": tiling_source},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "full_run": full,
+        "batched": batched,
         "served": served,
     }
     print(json.dumps(line), flush=True)

@@ -98,17 +98,22 @@ typedef struct {
   uint64_t moved_last; /* agents that moved in the last step */
 } sim_stats_t;
 
-/* Bytes of device scratch a scenario with these parameters needs
- * (1 byte per cell plus small per-tile counters). */
+/* Bytes of device scratch a scenario with these parameters needs: a shadow
+ * copy of the planes the step kernels ping-pong with (13 bytes per cell:
+ * code 1, id 4, both pheromone planes 8) plus per-tile counters and a few
+ * 64-bit totals. */
 int sim_scratch_bytes(const sim_params* p, size_t* out);
 
 /*
  * Create a handle over caller-owned device planes that hold the initial
  * state (layout above) and a device scratch buffer of at least
- * sim_scratch_bytes(). d_tau may be NULL (then only LEM steps are allowed).
- * The planes are validated on the device: codes in 0..3, ids consistent with
- * codes and exactly 1..N, pheromone finite and >= 0; a bad state returns
- * SIM_ESTATE. Synchronises `stream`.
+ * sim_scratch_bytes(). This is the paper's data-preparation stage
+ * (Sec. IV.a): the grid, the agents' groups and positions and the initial
+ * pheromone become the state every later step updates. d_tau may be NULL
+ * (then only LEM steps are allowed). The planes are validated on the
+ * device: codes in 0..3, ids consistent with codes and exactly 1..N,
+ * pheromone finite and >= 0; a bad state returns SIM_ESTATE. The initial
+ * counters are computed before the call returns. Synchronises `stream`.
  */
 int sim_create(const sim_params* p, uint8_t* d_code, uint32_t* d_id, float* d_tau,
                void* d_scratch, size_t scratch_bytes, void* stream, sim_handle** out);

@@ -301,6 +301,9 @@ int sim_batch_add(sim_batch* b, const sim_params* p, int32_t mode, uint8_t* d_co
   hs.t = p->step0;
   if (!slot_geometry(b->tl, hs, b->nb8)) return SIM_EINVAL;
   PEDSIM_HIP(launch_count(d_code, p->W, p->H, p->cross_a, p->cross_b, hs.stats, &hs.stats_entries, s));
+  // the slot's counters are complete once the call returns, so a step call on
+  // another stream may follow without an event
+  PEDSIM_HIP(hipStreamSynchronize(s));
   hs.used = true;
   b->slots[free_slot] = hs;
   if (mode == kModeAcoTour && !b->tour) {

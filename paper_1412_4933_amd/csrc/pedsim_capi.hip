@@ -263,6 +263,33 @@ int run_steps(sim_handle* h, int mode, int32_t nsteps, hipStream_t s, hipEvent_t
   return SIM_OK;
 }
 
+// Set up *h over the caller's planes and a scratch area laid out as L:
+// validate the state, then count the initial state; synchronises s, so the
+// handle's counters are complete (and the caller's planes no longer read)
+// whichever stream the next call uses.
+int init_handle(sim_handle* h, const sim_params* p, uint8_t* d_code, uint32_t* d_id, float* d_tau,
+                uint8_t* scratch, const ScratchLayout& L, hipStream_t s) {
+  const size_t cells = (size_t)p->W * (size_t)p->H;
+  uint64_t agents = 0;
+  const int e = validate_state(p, d_code, d_id, d_tau, scratch, L, s, &agents);
+  if (e) return e;
+  h->p = *p;
+  h->user = Planes{d_code, d_id, d_tau};
+  h->shadow = Planes{scratch + L.code2, (uint32_t*)(scratch + L.id2), d_tau ? (float*)(scratch + L.tau2) : nullptr};
+  h->stats = (uint32_t*)(scratch + L.stats);
+  h->stats_cap = L.stats_cap;
+  h->totals = (unsigned long long*)(scratch + L.totals);
+  h->t = p->step0;
+  h->agents = agents;
+  h->base = base_scenario(p);
+  h->tiling[kModeLem] = default_tiling(kModeLem, cells);
+  h->tiling[kModeAco] = default_tiling(kModeAco, cells);
+  h->tiling[kModeAcoTour] = default_tiling(kModeAcoTour, cells);
+  PEDSIM_HIP(launch_count(d_code, p->W, p->H, p->cross_a, p->cross_b, h->stats, &h->stats_entries, s));
+  PEDSIM_HIP(hipStreamSynchronize(s));
+  return SIM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -297,32 +324,12 @@ int sim_create(const sim_params* p, uint8_t* d_code, uint32_t* d_id, float* d_ta
   *out = nullptr;
   const ScratchLayout L = layout_of(p);
   if (!d_scratch || scratch_bytes < L.total) return SIM_ESCRATCH;
-  hipStream_t s = (hipStream_t)stream;
-  uint8_t* scratch = (uint8_t*)d_scratch;
-  const size_t cells = (size_t)p->W * (size_t)p->H;
-  uint64_t agents = 0;
-  e = validate_state(p, d_code, d_id, d_tau, scratch, L, s, &agents);
-  if (e) return e;
-  unsigned long long* totals = (unsigned long long*)(scratch + L.totals);
-
   sim_handle* h = new (std::nothrow) sim_handle;
   if (!h) return SIM_EINVAL;
-  h->p = *p;
-  h->user = Planes{d_code, d_id, d_tau};
-  h->shadow = Planes{scratch + L.code2, (uint32_t*)(scratch + L.id2), d_tau ? (float*)(scratch + L.tau2) : nullptr};
-  h->stats = (uint32_t*)(scratch + L.stats);
-  h->stats_cap = L.stats_cap;
-  h->totals = totals;
-  h->t = p->step0;
-  h->agents = agents;
-  h->base = base_scenario(p);
-  h->tiling[kModeLem] = default_tiling(kModeLem, cells);
-  h->tiling[kModeAco] = default_tiling(kModeAco, cells);
-  h->tiling[kModeAcoTour] = default_tiling(kModeAcoTour, cells);
-  const hipError_t e2 = launch_count(d_code, p->W, p->H, p->cross_a, p->cross_b, h->stats, &h->stats_entries, s);
-  if (e2 != hipSuccess) {
+  e = init_handle(h, p, d_code, d_id, d_tau, (uint8_t*)d_scratch, L, (hipStream_t)stream);
+  if (e) {
     delete h;
-    return hip_fail(e2, "launch_count", __LINE__);
+    return e;
   }
   *out = h;
   return SIM_OK;

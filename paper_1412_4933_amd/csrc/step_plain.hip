@@ -197,9 +197,17 @@ __global__ __launch_bounds__(256) void validate_cells_kernel(const uint8_t* code
       if (!(tb >= 0.0f && tb <= 3.402823466e38f)) bad = 1;
     }
   }
-  atomicAdd(&counters[0], na);
-  atomicAdd(&counters[1], nb);
-  if (bad) atomicOr(&counters[2], 1ull);
+  // one atomic per wave: sum the lanes' counts with cross-lane shuffles first
+  for (int off = 32; off > 0; off >>= 1) {
+    na += __shfl_down(na, off, 64);
+    nb += __shfl_down(nb, off, 64);
+  }
+  const bool any_bad = __ballot(bad != 0u) != 0ull;
+  if ((threadIdx.x & 63) == 0) {
+    if (na) atomicAdd(&counters[0], na);
+    if (nb) atomicAdd(&counters[1], nb);
+    if (any_bad) atomicOr(&counters[2], 1ull);
+  }
 }
 
 // Each agent id must be in 1..n and appear once: mark a bitmap.

@@ -20,6 +20,10 @@ LIB_PATH = os.path.join(_PKG, "libpedsim.so")
 SIM_OK, SIM_EINVAL, SIM_ESTATE, SIM_ESCRATCH, SIM_EHIP, SIM_ENOTAU, SIM_EFULL = 0, -1, -2, -3, -4, -5, -6
 SIM_ENOTOUR = -7
 SIM_MODE_LEM, SIM_MODE_ACO, SIM_MODE_ACO_TOUR = 0, 1, 2
+# A batch tuning (nw, rows, steps per launch, threads, workgroups per CU) of
+# the row-lane engine with the pheromone in LDS, which tour-variant scenarios
+# need before they can be added (the library's own default for that form).
+LDS_BATCH_TUNING = (0, 48, 3, 512, 2)
 
 
 class SimError(RuntimeError):
@@ -299,9 +303,12 @@ def params_of(s, step0: int = 0) -> SimParams:
 
 class Sim:
     """One scenario resident on the GPU: device planes allocated with torch,
-    stepped by the library."""
+    stepped by the library. With autotune=True (the default) the tilings the
+    autotuner's committed cache holds for this workload replace the library's
+    defaults."""
 
-    def __init__(self, scenario, device: str = "cuda", stream=None, step0: int = 0):
+    def __init__(self, scenario, device: str = "cuda", stream=None, step0: int = 0,
+                 autotune: bool = True):
         import torch
         self.torch = torch
         self.scenario = scenario
@@ -320,6 +327,18 @@ class Sim:
                             stream)
         if getattr(scenario, "neighbours", 5) != 5:
             sim_set_neighbours(self.h, scenario.neighbours)
+        self.tuned = {}
+        if autotune:
+            from . import autotune as tuner
+            for m in (SIM_MODE_LEM, SIM_MODE_ACO, SIM_MODE_ACO_TOUR):
+                tl = tuner.cached_plain(scenario, m)
+                if tl is None:
+                    continue
+                try:
+                    sim_set_tiling(self.h, m, *tl)
+                    self.tuned[m] = tuple(tl)
+                except SimError:  # not allowed on this device: keep the default
+                    pass
         # tour variant: the tour matrix (one float per agent) and its ping-pong half
         self.tour = self.tour_shadow = None
         if scenario.mode == SIM_MODE_ACO_TOUR or getattr(scenario, "tour", None) is not None:
@@ -398,6 +417,26 @@ class _Resident:
             self.tour = torch.from_numpy(np.ascontiguousarray(t0, dtype=np.float32)).to(device)
             self.tour_shadow = torch.empty_like(self.tour)
 
+    def clone(self) -> "_Resident":
+        """A device copy of these planes (and tour arrays) with scratch of its
+        own; nothing crosses PCIe."""
+        out = _Resident.__new__(_Resident)
+        out.scenario = self.scenario
+        out.params = params_of(self.scenario, int(self.params.step0))
+        out.code = self.code.clone()
+        out.ids = self.ids.clone()
+        out.tau = None if self.tau is None else self.tau.clone()
+        out.scratch_bytes = self.scratch_bytes
+        out.scratch = self.torch_empty_like(self.scratch)
+        out.tour = None if self.tour is None else self.tour.clone()
+        out.tour_shadow = None if self.tour_shadow is None else self.torch_empty_like(self.tour_shadow)
+        return out
+
+    @staticmethod
+    def torch_empty_like(t):
+        import torch
+        return torch.empty_like(t)
+
     def nbytes(self) -> int:
         n = self.code.numel() + 4 * self.ids.numel() + self.scratch_bytes
         n += 8 * self.tour.numel() if self.tour is not None else 0
@@ -412,9 +451,15 @@ class _Resident:
 
 class Batch:
     """Many scenarios resident on one GPU, advanced together by the batched
-    kernel. Device memory comes from torch; slots are the library's."""
+    kernel. Device memory comes from torch; slots are the library's.
 
-    def __init__(self, capacity: int, device: str = "cuda", stream=None):
+    With autotune=True (the default), the first step call applies the
+    autotuner's cached tuning for the resident scenarios if the committed
+    cache holds one and no tuning was set explicitly; `tuning_source` says
+    which tuning the batch runs ("library default", "autotuner cache" or
+    "explicit")."""
+
+    def __init__(self, capacity: int, device: str = "cuda", stream=None, autotune: bool = True):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -425,13 +470,18 @@ class Batch:
         self.b = sim_batch_create(capacity, self.workspace, nbytes)
         self.members = {}
         self.neighbours = 5
+        self.autotune = autotune
+        self.tuning_source = "library default"
 
     def add(self, scenario, mode: Optional[int] = None, step0: int = 0) -> int:
-        mode = scenario.mode if mode is None else mode
         if getattr(scenario, "neighbours", 5) != self.neighbours:
             raise ValueError(f"scenario uses {scenario.neighbours} neighbours, the batch "
                              f"{self.neighbours} (set_neighbours first)")
-        res = _Resident(scenario, self.device, step0)
+        return self.add_resident(_Resident(scenario, self.device, step0), mode)
+
+    def add_resident(self, res: "_Resident", mode: Optional[int] = None) -> int:
+        """Add a scenario whose planes are already on the device."""
+        mode = res.scenario.mode if mode is None else mode
         self.torch.cuda.synchronize(self.device)
         slot = sim_batch_add(self.b, res.params, mode, res.code, res.ids, res.tau, res.scratch,
                              res.scratch_bytes, self.stream)
@@ -440,15 +490,30 @@ class Batch:
         self.members[slot] = res
         return slot
 
+    def _autotune(self) -> None:
+        if not self.autotune or self.tuning_source != "library default" or not self.members:
+            return
+        self.autotune = False  # looked up once, for the first call's residents
+        from . import autotune as tuner
+        tu = tuner.cached_batch([r.scenario for r in self.members.values()])
+        if tu is not None:
+            try:
+                sim_batch_set_tuning(self.b, *tu, 1)
+                self.tuning_source = "autotuner cache"
+            except SimError:  # not allowed on this device or for these residents
+                pass
+
     def remove(self, slot: int) -> None:
         sim_batch_remove(self.b, slot)
         self.members.pop(slot, None)
 
     def step(self, nsteps: int) -> None:
+        self._autotune()
         sim_batch_step(self.b, nsteps, self.stream)
 
     def step_slots(self, steps) -> None:
         """steps: list indexed by slot, or {slot: steps}."""
+        self._autotune()
         if isinstance(steps, dict):
             arr = [0] * self.capacity
             for k, v in steps.items():
@@ -466,6 +531,7 @@ class Batch:
 
     def set_tuning(self, nw, rows, steps_per_launch, threads, wgs_per_cu, use_graph=1) -> None:
         sim_batch_set_tuning(self.b, nw, rows, steps_per_launch, threads, wgs_per_cu, use_graph)
+        self.tuning_source = "explicit"
 
     def tuning(self):
         return sim_batch_get_tuning(self.b)
@@ -474,8 +540,10 @@ class Batch:
         for res in self.members.values():
             if getattr(res.scenario, "neighbours", 5) != n:
                 raise ValueError("a resident scenario uses another candidate set")
-        sim_batch_set_neighbours(self.b, n)
+        sim_batch_set_neighbours(self.b, n)  # resets the tuning to that set's default
         self.neighbours = n
+        if self.tuning_source == "explicit":
+            self.tuning_source = "library default"
 
     def tour_lengths(self, slot: int) -> np.ndarray:
         """The tour matrix of a tour-variant slot on the host."""

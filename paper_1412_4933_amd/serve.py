@@ -35,6 +35,7 @@ class Request:
     nbytes: int             # device bytes the request holds while resident
     agents: int
     scenario: Optional["scenarios.Scenario"] = None  # the initial state, when it came with the request
+    mode: Optional[int] = None  # SIM_MODE_* of the scenario (None: read from its initial state)
 
 
 @dataclasses.dataclass
@@ -46,18 +47,22 @@ class Result:
     steps: int
     agents: int
     stats: dict
-    state: Optional[tuple] = None
+    state: Optional[tuple] = None  # (code, ids, tau) with keep_state
+    tour: Optional[np.ndarray] = None  # tour matrix of a tour-variant request, with keep_state
 
     @property
     def latency(self) -> float:
         return self.finished - self.arrival
 
 
-def resident_bytes(W: int, H: int, aco: bool) -> int:
+def resident_bytes(W: int, H: int, mode: int, agents: int = 0) -> int:
     """Device bytes one scenario holds: code + id planes, pheromone planes
-    (ACO), and the library's scratch."""
+    (ACO and the tour variant), the tour matrix and its ping-pong half (tour
+    variant, 4 B each per agent), and the library's scratch."""
     p = pedsim.SimParams(W, H, 0, 0, 0.1, 1.0, 1, 2, 0, 0)
-    return W * H * (1 + 4 + (8 if aco else 0)) + pedsim.sim_scratch_bytes(p)
+    aco = mode in (scenarios.MODE_ACO, scenarios.MODE_ACO_TOUR)
+    tour = 8 * agents if mode == scenarios.MODE_ACO_TOUR else 0
+    return W * H * (1 + 4 + (8 if aco else 0)) + tour + pedsim.sim_scratch_bytes(p)
 
 
 def prebuild(requests: List[Request]) -> None:
@@ -72,6 +77,10 @@ def _initial_state(req: Request) -> "scenarios.Scenario":
     return req.scenario if req.scenario is not None else req.build()
 
 
+def _request_mode(req: Request) -> int:
+    return req.mode if req.mode is not None else _initial_state(req).mode
+
+
 def poisson_requests(specs, rate: float, seed: int = 0) -> List[Request]:
     """specs: (W, H, N, band, mode, steps, seed) tuples; arrivals of a Poisson
     process with `rate` requests per second."""
@@ -84,7 +93,7 @@ def poisson_requests(specs, rate: float, seed: int = 0) -> List[Request]:
         def build(W=W, H=H, N=N, band=band, mode=mode, sseed=sseed):
             return scenarios.make_scenario(W, H, N // 2, N - N // 2, band_a=band, seed=sseed, mode=mode)
 
-        out.append(Request(rid, t, steps, build, resident_bytes(W, H, mode == scenarios.MODE_ACO), N))
+        out.append(Request(rid, t, steps, build, resident_bytes(W, H, mode, N), N, mode=mode))
     return out
 
 
@@ -97,6 +106,7 @@ class Server:
         self.stream = torch.cuda.Stream(self.device)
         self.side = torch.cuda.Stream(self.device)
         self.batch = pedsim.Batch(capacity, device=device, stream=self.stream)
+        self.tuning = tuning
         if tuning is not None:
             self.batch.set_tuning(*tuning)
         self.capacity = capacity
@@ -113,11 +123,17 @@ class Server:
         self.side.synchronize()
         slot = pedsim.sim_batch_add(self.batch.b, res.params, scn.mode, res.code, res.ids, res.tau,
                                     res.scratch, res.scratch_bytes, self.side)
+        if res.tour is not None and res.tour.numel():
+            pedsim.sim_batch_attach_tour(self.batch.b, slot, res.tour, res.tour_shadow, self.side)
         self.batch.members[slot] = res
         self.live[slot] = [req, req.steps, now]
         self.used += req.nbytes
 
     def run(self, requests: List[Request], clock=time.perf_counter) -> List[Result]:
+        if self.tuning is None and not self.live and any(
+                _request_mode(r) == scenarios.MODE_ACO_TOUR for r in requests):
+            # tour-variant scenarios run on the batch's LDS form only
+            self.batch.set_tuning(*pedsim.LDS_BATCH_TUNING)
         pending = sorted(requests, key=lambda r: r.arrival)
         queue: List[Request] = []
         results: List[Result] = []
@@ -153,9 +169,11 @@ class Server:
                 if entry[1] == 0:
                     req = entry[0]
                     stats = pedsim.sim_batch_stats(self.batch.b, slot, self.stream)
-                    state = self.batch.members[slot].state() if self.keep_state else None
+                    res = self.batch.members[slot]
+                    state = res.state() if self.keep_state else None
+                    tour = res.tour.cpu().numpy() if self.keep_state and res.tour is not None else None
                     results.append(Result(req.rid, req.arrival, entry[2], done_time, req.steps, req.agents,
-                                          stats, state))
+                                          stats, state, tour))
                     self.batch.remove(slot)
                     del self.live[slot]
                     self.used -= req.nbytes

@@ -67,3 +67,40 @@ def test_served_request_larger_than_budget_is_refused(mods):
     with pytest.raises(ValueError):
         srv.run(reqs)
     srv.close()
+
+
+def test_served_tour_variant_requests(mods):
+    """Requests of all three modes, the tour variant among them, are admitted
+    (the tour matrix is counted in their bytes and attached to their slot) and
+    each result, tour lengths included, equals the oracle's."""
+    pedsim, serve = mods
+    rng = np.random.default_rng(23)
+    specs = []
+    for i in range(9):
+        W = int(rng.integers(40, 160))
+        H = int(rng.integers(10, 60))
+        N = int(rng.integers(20, min(2 * (W // 4) * (H - 2), 1500)))
+        specs.append((W, H, N, max(1, W // 10), (S.MODE_LEM, S.MODE_ACO, S.MODE_ACO_TOUR)[i % 3],
+                      int(rng.integers(10, 90)), 700 + i))
+    reqs = serve.poisson_requests(specs, rate=300.0, seed=4)
+    for r, spec in zip(reqs, specs):
+        if spec[4] == S.MODE_ACO_TOUR:
+            W, H, N = spec[:3]
+            assert r.nbytes == serve.resident_bytes(W, H, S.MODE_ACO, N) + 8 * N
+    print("[gpu-case] served tour", len(reqs), flush=True)
+    srv = serve.Server(capacity=3, budget_bytes=1 << 30, quantum=12, keep_state=True)
+    results = srv.run(reqs)
+    srv.close()
+    assert sorted(r.rid for r in results) == list(range(len(reqs)))
+    for res in results:
+        req = reqs[res.rid]
+        scn = req.build()
+        st = oracle.State.from_scenario(scn)
+        st.run(scn.mode, req.steps)
+        code, ids, tau = res.state
+        assert np.array_equal(code, st.code) and np.array_equal(ids, st.ids), req.rid
+        if scn.mode != S.MODE_LEM:
+            assert np.array_equal(tau.view(np.uint32), st.tau.view(np.uint32)), req.rid
+        if scn.mode == S.MODE_ACO_TOUR:
+            assert np.array_equal(res.tour.view(np.uint32), st.tour.view(np.uint32)), req.rid
+        assert res.stats["step"] == req.steps
