@@ -100,6 +100,19 @@ def lib(parallel: bool = False):
                                       ctypes.c_void_p, ctypes.c_void_p]
         L.oracle_run_tour.restype = ctypes.c_int64
         L.oracle_counts.argtypes = [P(OracleParams), ctypes.c_void_p, P(ctypes.c_uint64)]
+        L.oracle_step_range.argtypes = [P(OracleParams), ctypes.c_int32, ctypes.c_uint64,
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p]
+        L.oracle_step_range.restype = ctypes.c_int64
+        L.oracle_run_range.argtypes = [P(OracleParams), ctypes.c_int32, ctypes.c_uint64,
+                                       ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]
+        L.oracle_run_range.restype = ctypes.c_int64
+        L.oracle_range_weights.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           P(ctypes.c_float), P(ctypes.c_float)]
+        L.oracle_range_weights.restype = None
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_set_threads.restype = ctypes.c_int
         _libs[parallel] = L
@@ -126,6 +139,15 @@ def lem_thresholds():
     return tuple(int(v) for v in o)
 
 
+def range_weights(S: int, M: int, beta: int):
+    """eta^beta of the side rays with ranges (S, M): (diagonal, lateral),
+    each indexed by the free run f - 1 for f = 1..S."""
+    d = (ctypes.c_float * 8)()
+    la = (ctypes.c_float * 8)()
+    lib().oracle_range_weights(int(S), int(M), int(beta), d, la)
+    return ([np.float32(v) for v in d[:S]], [np.float32(v) for v in la[:S]])
+
+
 def heuristic_weights(beta: int):
     """(eta^beta) for the forward, diagonal, lateral, backward and backward
     diagonal candidates."""
@@ -145,7 +167,7 @@ class State:
     def __init__(self, code, ids, tau=None, *, seed: int, rho: float = 0.1,
                  dtau: float = 1.0, alpha: int = 1, beta: int = 2, cross_a: int = 1,
                  cross_b: int = 1, t: int = 0, tour=None, neighbours: int = 5,
-                 threads: Optional[int] = None):
+                 threads: Optional[int] = None, ranges: Optional[Tuple[int, int]] = None):
         self.code = np.ascontiguousarray(code, dtype=np.uint8).copy()
         self.ids = np.ascontiguousarray(ids, dtype=np.uint32).copy()
         self.H, self.W = self.code.shape
@@ -164,13 +186,16 @@ class State:
                               cross_b, neighbours)
         self.t = t
         self.threads = threads
+        # (scanning range S, moving range M): steps follow the range model
+        # (oracle_step_range), also for (1, 1); None: the base step
+        self.ranges = None if ranges is None else (int(ranges[0]), int(ranges[1]))
 
     @classmethod
     def from_scenario(cls, s, threads: Optional[int] = None) -> "State":
         return cls(s.code, s.ids, s.tau, seed=s.seed, rho=s.rho, dtau=s.dtau,
                    alpha=s.alpha, beta=s.beta, cross_a=s.cross_a, cross_b=s.cross_b,
                    tour=getattr(s, "tour", None), neighbours=getattr(s, "neighbours", 5),
-                   threads=threads)
+                   threads=threads, ranges=getattr(s, "ranges", None))
 
     def _lib(self):
         """The build this state runs on; the OpenMP build's thread count is a
@@ -189,8 +214,25 @@ class State:
         return None, None
 
     def step(self, mode: int, want_detail: bool = False):
-        """One step; returns moved, or (moved, req, win) with want_detail."""
+        """One step; returns moved, or (moved, req, win) with want_detail
+        (with ranges: (moved, ray, length))."""
         ta, tb = self._tau_ptrs(mode)
+        if self.ranges is not None:
+            req = length = None
+            if want_detail:
+                req = np.zeros((self.H, self.W), dtype=np.uint8)
+                length = np.zeros((self.H, self.W), dtype=np.uint8)
+            moved = self._lib().oracle_step_range(
+                ctypes.byref(self.p), mode, self.t, self.ranges[0], self.ranges[1],
+                self.code.ctypes.data, self.ids.ctypes.data, ta, tb,
+                None if req is None else req.ctypes.data,
+                None if length is None else length.ctypes.data)
+            if moved == -2:
+                raise ValueError(f"bad ranges {self.ranges} or mode {mode}")
+            if moved < 0:
+                raise MemoryError("oracle step failed to allocate")
+            self.t += 1
+            return (moved, req, length) if want_detail else moved
         req = win = None
         if want_detail:
             req = np.zeros((self.H, self.W), dtype=np.uint8)
@@ -212,6 +254,16 @@ class State:
 
     def run(self, mode: int, nsteps: int) -> int:
         ta, tb = self._tau_ptrs(mode)
+        if self.ranges is not None:
+            moved = self._lib().oracle_run_range(ctypes.byref(self.p), mode, self.t, nsteps,
+                                                 self.ranges[0], self.ranges[1],
+                                                 self.code.ctypes.data, self.ids.ctypes.data, ta, tb)
+            if moved == -2:
+                raise ValueError(f"bad ranges {self.ranges} or mode {mode}")
+            if moved < 0:
+                raise MemoryError("oracle step failed to allocate")
+            self.t += nsteps
+            return moved
         if mode == MODE_ACO_TOUR:
             moved = self._lib().oracle_run_tour(ctypes.byref(self.p), self.t, nsteps,
                                           self.code.ctypes.data, self.ids.ctypes.data, ta, tb,

@@ -62,6 +62,8 @@
  *     float addition; the cell the agent enters gains fl(dtau / L_k) with the
  *     increased L_k (dtau = 1 gives eq. 5's 1/L_k), after its evaporation;
  *     agents that stay deposit nothing.
+ *   - larger scanning and moving ranges (oracle_step_range): see the block
+ *     before that function.
  * All float arithmetic is IEEE binary32, one operation at a time, without
  * contraction into fused multiply-adds (built with -ffp-contract=off) and
  * with subnormals kept.
@@ -444,6 +446,288 @@ static int64_t step_any(const oracle_params *p, int32_t mode, uint64_t t, uint8_
   free(new_code);
   free(new_id);
   free(entered);
+  return moved;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Larger scanning and moving ranges (the paper's future work, Sec. VII).     */
+/* Scanning range S and moving range M (1 <= M <= S): the five candidate      */
+/* directions become rays. Along each ray the agent sees the free run f, the  */
+/* number of consecutive cells next to it that are inside the grid and empty  */
+/* at t (at most S); an open ray (f >= 1) is travelled k = min(f, M) cells.   */
+/* The distance of Sec. IV.a-b is taken from the landing cell to the point    */
+/* M+1 cells ahead; LEM (eq. 1) reads the occupancy of a candidate as the     */
+/* blocked share of its scanned ray, 1 - f/S, and ACO (eq. 2) weighs the      */
+/* pheromone of the landing cell with the heuristic (f/S)/D. With S = M = 1   */
+/* every rule reduces to the steps above.                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Ray r (0 F, 1 FD-, 2 FD+, 3 L-, 4 L+) of an agent heading d: its forward
+ * component a (1 or 0), lateral component b, and unit step (ux, uy). */
+static void range_ray(int r, int d, int *a, int *b, int *ux, int *uy) {
+  static const int fwd[5] = {1, 1, 1, 0, 0};
+  static const int lat[5] = {0, -1, 1, -1, 1};
+  *a = fwd[r];
+  *b = lat[r];
+  *ux = d * fwd[r];
+  *uy = lat[r];
+}
+
+/* Free run along the unit step (ux, uy) from (x, y), at most S cells. */
+static int free_run(const oracle_params *p, const uint8_t *code, int x, int y, int ux, int uy,
+                    int S) {
+  int j = 0;
+  while (j < S && free_cell(p, code, x + (j + 1) * ux, y + (j + 1) * uy)) j += 1;
+  return j;
+}
+
+/* Squared distance from the cell k steps along a ray with components (a, b)
+ * to the point M+1 cells ahead of the agent. */
+static int64_t range_d2(int a, int b, int k, int M) {
+  int64_t dx = (int64_t)(M + 1) - (int64_t)a * k;
+  int64_t dy = (int64_t)b * k;
+  return dx * dx + dy * dy;
+}
+
+/* eta^beta of a side ray with forward component a and free run f >= 1:
+ * (f/S)^beta * D2^(-beta/2), rounded to float. */
+static float range_weight(int a, int f, int S, int M, int beta) {
+  int k = f < M ? f : M;
+  double d2 = (double)range_d2(a, 1, k, M);
+  return (float)(pow((double)f / (double)S, (double)beta) * pow(d2, -0.5 * (double)beta));
+}
+
+void oracle_range_weights(int32_t S, int32_t M, int32_t beta, float out_diagonal[8],
+                          float out_lateral[8]) {
+  int f;
+  for (f = 1; f <= 8; ++f) {
+    out_diagonal[f - 1] = f <= S ? range_weight(1, f, S, M, beta) : 0.0f;
+    out_lateral[f - 1] = f <= S ? range_weight(0, f, S, M, beta) : 0.0f;
+  }
+}
+
+/* LEM with ranges: open side rays (f[i] >= 1 for side ray i = 1..4) ranked by
+ * C = (f/S)(Dmin/D), highest first, ties in the order [FD_s, FD_-s, L_s, L_-s];
+ * returns the chosen ray (1..4), or 0 if none is open. */
+static int range_lem_choice(const int f[5], const int64_t d2[5], uint32_t r1, uint32_t r2) {
+  const int minus_first[4] = {1, 2, 3, 4};
+  const int plus_first[4] = {2, 1, 4, 3};
+  const int *order = (r2 & 1u) ? plus_first : minus_first;
+  int ranked[4];
+  int n = 0, i, j, index;
+  for (i = 0; i < 4; ++i) {
+    int r = order[i];
+    if (f[r] < 1) continue;
+    /* insertion: move past every ranked ray with a strictly higher score */
+    j = n;
+    while (j > 0) {
+      int q = ranked[j - 1];
+      /* C_q < C_r  <=>  f_q^2 D2_r < f_r^2 D2_q */
+      if ((int64_t)f[q] * f[q] * d2[r] < (int64_t)f[r] * f[r] * d2[q]) {
+        ranked[j] = q;
+        j -= 1;
+      } else {
+        break;
+      }
+    }
+    ranked[j] = r;
+    n += 1;
+  }
+  if (n == 0) return 0;
+  index = 0;
+  for (i = 0; i < 3; ++i)
+    if (r1 >= lem_threshold[i]) index += 1;
+  if (index > n - 1) index = n - 1;
+  return ranked[index];
+}
+
+/* ACO with ranges: roulette over the side rays 1..4 with weights
+ * tau(landing cell)^alpha * eta^beta; all-zero weights fall back to LEM. */
+static int range_aco_choice(const int f[5], const int64_t d2[5], const float tau[5],
+                            const float eta[5], int alpha, uint32_t r1, uint32_t r2) {
+  float w[5];
+  float sum, u, target, running;
+  int i, last;
+  for (i = 1; i <= 4; ++i) {
+    if (f[i] >= 1) {
+      float power = 1.0f;
+      int a;
+      if (alpha > 0) {
+        power = tau[i];
+        for (a = 1; a < alpha; ++a) power = power * tau[i];
+      }
+      w[i] = power * eta[i];
+    } else {
+      w[i] = 0.0f;
+    }
+  }
+  sum = w[1];
+  for (i = 2; i <= 4; ++i) sum = sum + w[i];
+  if (sum == 0.0f) return range_lem_choice(f, d2, r1, r2);
+  u = (float)(r1 >> 8) * 0x1p-24f;
+  target = u * sum;
+  running = 0.0f;
+  last = -1;
+  for (i = 1; i <= 4; ++i) {
+    running = running + w[i];
+    if (w[i] > 0.0f) {
+      last = i;
+      if (target < running) return i;
+    }
+  }
+  return last;
+}
+
+/*
+ * One step with scanning range S and moving range M, in place; mode 0 = LEM,
+ * 1 = ACO (tau planes required). req_out (optional, H*W bytes): each agent's
+ * ray + 1 (1 F, 2 FD-, 3 FD+, 4 L-, 5 L+) or 0; len_out (optional, H*W
+ * bytes): the cells it asked to travel. Returns the number of agents that
+ * moved, -1 on allocation failure, -2 on bad ranges.
+ */
+int64_t oracle_step_range(const oracle_params *p, int32_t mode, uint64_t t, int32_t S, int32_t M,
+                          uint8_t *code, uint32_t *id, float *tau_a, float *tau_b,
+                          uint8_t *req_out, uint8_t *len_out) {
+  const int W = p->W, H = p->H;
+  const size_t cells = (size_t)W * (size_t)H;
+  uint8_t *ray, *len, *new_code;
+  uint32_t *new_id;
+  int64_t moved = 0;
+  int x, y;
+  if (S < 1 || S > 8 || M < 1 || M > S || (mode != 0 && mode != 1)) return -2;
+  ray = (uint8_t *)calloc(cells, 1);
+  len = (uint8_t *)calloc(cells, 1);
+  new_code = (uint8_t *)malloc(cells);
+  new_id = (uint32_t *)malloc(cells * sizeof(uint32_t));
+  if (!ray || !len || !new_code || !new_id) {
+    free(ray);
+    free(len);
+    free(new_code);
+    free(new_id);
+    return -1;
+  }
+
+  /* 1. request: every agent on the snapshot of time t */
+#pragma omp parallel for private(x) schedule(static)
+  for (y = 0; y < H; ++y)
+    for (x = 0; x < W; ++x) {
+      size_t c = (size_t)y * W + x;
+      int g = code[c], d, r, choice, any = 0;
+      int f[5], a[5], b[5], ux[5], uy[5];
+      int64_t d2[5];
+      float eta[5], tau[5];
+      uint32_t w[4];
+      if (g != O_A && g != O_B) continue;
+      d = heading(g);
+      for (r = 0; r < 5; ++r) {
+        range_ray(r, d, &a[r], &b[r], &ux[r], &uy[r]);
+        f[r] = free_run(p, code, x, y, ux[r], uy[r], S);
+        d2[r] = range_d2(a[r], b[r], f[r] < M ? f[r] : M, M);
+        if (r > 0 && f[r] >= 1) any = 1;
+      }
+      if (f[0] >= 1) {
+        choice = 0; /* forward first */
+      } else {
+        if (!any) continue;
+        agent_words(p->seed, t, id[c] - 1u, w);
+        if (mode == 0) {
+          choice = range_lem_choice(f, d2, w[1], w[2]);
+        } else {
+          const float *plane = (g == O_A) ? tau_a : tau_b;
+          for (r = 1; r <= 4; ++r) {
+            eta[r] = 0.0f;
+            tau[r] = 0.0f;
+            if (f[r] >= 1) {
+              int k = f[r] < M ? f[r] : M;
+              eta[r] = range_weight(a[r], f[r], S, M, p->beta);
+              tau[r] = plane[(size_t)(y + k * uy[r]) * W + (size_t)(x + k * ux[r])];
+            }
+          }
+          choice = range_aco_choice(f, d2, tau, eta, p->alpha, w[1], w[2]);
+        }
+      }
+      ray[c] = (uint8_t)(choice + 1);
+      len[c] = (uint8_t)(f[choice] < M ? f[choice] : M);
+    }
+
+  /* 2.+3. resolve every cell empty at t among the agents (up to M cells
+   * away) landing on it, then commit into fresh planes */
+  memcpy(new_code, code, cells);
+  memcpy(new_id, id, cells * sizeof(uint32_t));
+#pragma omp parallel for private(x) reduction(+ : moved) schedule(static)
+  for (y = 0; y < H; ++y)
+    for (x = 0; x < W; ++x) {
+      size_t c = (size_t)y * W + x;
+      int dx, dy, have = 0;
+      size_t best_n = 0;
+      uint32_t best_ticket = 0, best_k = 0;
+      if (code[c] != O_EMPTY) continue;
+      for (dy = -M; dy <= M; ++dy)
+        for (dx = -M; dx <= M; ++dx) {
+          int nx = x + dx, ny = y + dy, a, b, ux, uy, k;
+          size_t n;
+          if ((dx == 0 && dy == 0) || !inside(p, nx, ny)) continue;
+          n = (size_t)ny * W + nx;
+          if (code[n] != O_A && code[n] != O_B) continue;
+          if (ray[n] == 0) continue;
+          range_ray(ray[n] - 1, heading(code[n]), &a, &b, &ux, &uy);
+          k = len[n];
+          if (nx + k * ux != x || ny + k * uy != y) continue;
+          {
+            uint32_t w[4];
+            uint32_t kk = id[n] - 1u;
+            agent_words(p->seed, t, kk, w);
+            if (!have || w[0] < best_ticket || (w[0] == best_ticket && kk < best_k)) {
+              have = 1;
+              best_ticket = w[0];
+              best_k = kk;
+              best_n = n;
+            }
+          }
+        }
+      if (have) {
+        new_code[c] = code[best_n];
+        new_id[c] = id[best_n];
+        new_code[best_n] = O_EMPTY;
+        new_id[best_n] = 0;
+        moved += 1;
+      }
+    }
+  if (req_out) memcpy(req_out, ray, cells);
+  if (len_out) memcpy(len_out, len, cells);
+  memcpy(code, new_code, cells);
+  memcpy(id, new_id, cells * sizeof(uint32_t));
+
+  /* 4. pheromone: evaporation (eq. 3) then deposit (eq. 4), both planes */
+  if (mode == 1) {
+    float rho = p->rho;
+    float keep = 1.0f - rho;
+    size_t c;
+#pragma omp parallel for schedule(static)
+    for (c = 0; c < cells; ++c) {
+      float va = keep * tau_a[c];
+      float vb = keep * tau_b[c];
+      if (code[c] == O_A) va = va + p->dtau;
+      if (code[c] == O_B) vb = vb + p->dtau;
+      tau_a[c] = va;
+      tau_b[c] = vb;
+    }
+  }
+  free(ray);
+  free(len);
+  free(new_code);
+  free(new_id);
+  return moved;
+}
+
+int64_t oracle_run_range(const oracle_params *p, int32_t mode, uint64_t t0, int64_t nsteps,
+                         int32_t S, int32_t M, uint8_t *code, uint32_t *id, float *tau_a,
+                         float *tau_b) {
+  int64_t s, moved = 0;
+  for (s = 0; s < nsteps; ++s) {
+    moved = oracle_step_range(p, mode, t0 + (uint64_t)s, S, M, code, id, tau_a, tau_b, NULL, NULL);
+    if (moved < 0) return moved;
+  }
   return moved;
 }
 

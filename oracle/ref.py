@@ -183,3 +183,135 @@ def step(code, ids, tau, *, mode, t, seed, rho, dtau, alpha, beta, tour=None, ne
                         v = F32(v + F32(dtau))
                     plane[y, x] = v
     return new_code, new_ids, tau, req, len(best)
+
+
+# --- larger scanning and moving ranges (Sec. VII) -----------------------------
+
+RAY = {1: (1, 0), 2: (1, -1), 3: (1, 1), 4: (0, -1), 5: (0, 1)}  # (forward, lateral) unit steps
+
+
+def range_weight(a, f, S, M, beta):
+    """eta^beta of a side ray (forward component a, free run f): the float
+    nearest to (f/S)^beta * D2^(-beta/2), D2 from the landing cell to the
+    point M+1 cells ahead."""
+    k = min(f, M)
+    d2 = (M + 1 - a * k) ** 2 + k * k
+    return F32((f / S) ** beta * float(d2) ** (-0.5 * beta))
+
+
+def step_range(code, ids, tau, *, mode, t, seed, rho, dtau, alpha, beta, S, M):
+    """One step with scanning range S and moving range M on copies; returns
+    (code, ids, tau, req, length, moved). Requesters register at their landing
+    cell (scatter); the ranking sorts the open rays by the exact rational
+    score f^2 / D2 (the square of C up to a common factor)."""
+    from fractions import Fraction
+    H, W = code.shape
+    code, ids = code.copy(), ids.copy()
+    tau = None if tau is None else tau.copy()
+    key = (seed & MASK, seed >> 32)
+
+    def words(k):
+        return philox4x32_10((k, t & MASK, t >> 32, 0), key)
+
+    def empty(x, y):
+        return 0 <= x < W and 0 <= y < H and code[y, x] == 0
+
+    req = np.zeros((H, W), dtype=np.uint8)
+    length = np.zeros((H, W), dtype=np.uint8)
+    for y in range(H):
+        for x in range(W):
+            g = int(code[y, x])
+            if g not in (1, 2):
+                continue
+            d = 1 if g == 1 else -1
+            run = {}
+            for r, (a, b) in RAY.items():
+                n = 0
+                while n < S and empty(x + (n + 1) * a * d, y + (n + 1) * b):
+                    n += 1
+                run[r] = n
+            if run[1] >= 1:
+                req[y, x], length[y, x] = 1, min(run[1], M)
+                continue
+            open_rays = [r for r in (2, 3, 4, 5) if run[r] >= 1]
+            if not open_rays:
+                continue
+            w = words(int(ids[y, x]) - 1)
+
+            def d2(r):
+                a, b = RAY[r]
+                k = min(run[r], M)
+                return (M + 1 - a * k) ** 2 + (b * k) ** 2
+
+            def lem():
+                order = [3, 2, 5, 4] if (w[2] & 1) else [2, 3, 4, 5]
+                ranked = sorted([r for r in order if run[r] >= 1],
+                                key=lambda r: -Fraction(run[r] ** 2, d2(r)))
+                idx = sum(1 for th in THRESHOLDS[:3] if w[1] >= th)
+                return ranked[min(idx, len(ranked) - 1)]
+
+            if mode == 0:
+                pick = lem()
+            else:
+                plane = tau[g - 1]
+                ws = []
+                for r in (2, 3, 4, 5):
+                    if run[r] < 1:
+                        ws.append(F32(0.0))
+                        continue
+                    a, b = RAY[r]
+                    k = min(run[r], M)
+                    tv = F32(plane[y + k * b, x + k * a * d])
+                    p = F32(1.0)
+                    if alpha > 0:
+                        p = tv
+                        for _ in range(alpha - 1):
+                            p = F32(p * tv)
+                    ws.append(F32(p * range_weight(a, run[r], S, M, beta)))
+                tot = ws[0]
+                for wv in ws[1:]:
+                    tot = F32(tot + wv)
+                if tot == F32(0.0):
+                    pick = lem()
+                else:
+                    target = F32(F32(F32(w[1] >> 8) * F32(2.0 ** -24)) * tot)
+                    acc, pick, last = F32(0.0), None, None
+                    for i, r in enumerate((2, 3, 4, 5)):
+                        acc = F32(acc + ws[i])
+                        if ws[i] > 0:
+                            last = r
+                            if target < acc:
+                                pick = r
+                                break
+                    pick = pick if pick is not None else last
+            req[y, x], length[y, x] = pick, min(run[pick], M)
+
+    best = {}
+    for y in range(H):
+        for x in range(W):
+            r = int(req[y, x])
+            if r == 0:
+                continue
+            d = 1 if code[y, x] == 1 else -1
+            a, b = RAY[r]
+            k = int(length[y, x])
+            tx, ty = x + k * a * d, y + k * b
+            kk = int(ids[y, x]) - 1
+            cand = (words(kk)[0], kk, x, y)
+            if (tx, ty) not in best or cand[:2] < best[(tx, ty)][:2]:
+                best[(tx, ty)] = cand
+    new_code, new_ids = code.copy(), ids.copy()
+    for (tx, ty), (_, _, sx, sy) in best.items():
+        new_code[ty, tx], new_ids[ty, tx] = code[sy, sx], ids[sy, sx]
+        new_code[sy, sx], new_ids[sy, sx] = 0, 0
+    if mode == 1:
+        keep = F32(F32(1.0) - F32(rho))
+        for g in (1, 2):
+            plane = tau[g - 1]
+            for y in range(H):
+                for x in range(W):
+                    v = F32(keep * plane[y, x])
+                    if new_code[y, x] == g:
+                        v = F32(v + F32(dtau))
+                    plane[y, x] = v
+    return new_code, new_ids, tau, req, length, len(best)

@@ -62,6 +62,28 @@ MUTANTS = {
                                   "if (x <= p->cross_a) crossed_b += 1;"),
     "crossing_b_band_swapped": ("if (x < p->cross_a) crossed_b += 1;",
                                 "if (x < p->cross_b) crossed_b += 1;"),
+    # larger scanning and moving ranges
+    "range_scan_limited_to_move": ("f[r] = free_run(p, code, x, y, ux[r], uy[r], S);",
+                                   "f[r] = free_run(p, code, x, y, ux[r], uy[r], M);"),
+    "range_move_not_capped": ("len[c] = (uint8_t)(f[choice] < M ? f[choice] : M);",
+                              "len[c] = (uint8_t)(f[choice]);"),
+    "range_score_reversed": ("if ((int64_t)f[q] * f[q] * d2[r] < (int64_t)f[r] * f[r] * d2[q]) {",
+                             "if ((int64_t)f[q] * f[q] * d2[r] > (int64_t)f[r] * f[r] * d2[q]) {"),
+    "range_score_ignores_run": ("if ((int64_t)f[q] * f[q] * d2[r] < (int64_t)f[r] * f[r] * d2[q]) {",
+                                "if (d2[r] < d2[q]) {"),
+    "range_reference_two_ahead": ("int64_t dx = (int64_t)(M + 1) - (int64_t)a * k;",
+                                  "int64_t dx = (int64_t)2 - (int64_t)a * k;"),
+    "range_weight_ignores_visibility": (
+        "return (float)(pow((double)f / (double)S, (double)beta) * pow(d2, -0.5 * (double)beta));",
+        "return (float)(pow(d2, -0.5 * (double)beta));"),
+    "range_tau_next_to_agent": ("tau[r] = plane[(size_t)(y + k * uy[r]) * W + (size_t)(x + k * ux[r])];",
+                                "tau[r] = plane[(size_t)(y + uy[r]) * W + (size_t)(x + ux[r])];"),
+    "range_forward_not_first": ("      if (f[0] >= 1) {\n        choice = 0; /* forward first */",
+                                "      if (0) {\n        choice = 0; /* forward first */"),
+    "range_gather_radius_one": ("for (dy = -M; dy <= M; ++dy)\n        for (dx = -M; dx <= M; ++dx) {",
+                                "for (dy = -1; dy <= 1; ++dy)\n        for (dx = -1; dx <= 1; ++dx) {"),
+    "range_winner_highest_ticket": ("if (!have || w[0] < best_ticket || (w[0] == best_ticket && kk < best_k)) {",
+                                    "if (!have || w[0] > best_ticket || (w[0] == best_ticket && kk < best_k)) {"),
 }
 
 
@@ -81,6 +103,7 @@ def test_planted_mistake_fails_a_pin(name):
                         "-o", mlib, msrc, "-lm"], check=True)
         env = dict(os.environ, PEDSIM_ORACLE_LIB=mlib)
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                            os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                            os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                            os.path.join(ROOT, "tests", "test_oracle_range_pins.py")],
                            cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
         assert r.returncode != 0, f"mutant {name} passed every pin"
