@@ -18,23 +18,27 @@ SRC = os.path.join(ROOT, "oracle", "pedsim_oracle.c")
 MUTANTS = {
     "philox_high_halves_swapped": ("x0 = hi1 ^ x1 ^ k0;", "x0 = hi0 ^ x1 ^ k0;"),
     "philox_key_bumped_before_first_round": ("if (round > 0) {", "if (round >= 0) {"),
-    "lem_side_order_ignored": ("(r2 & 1u) ? plus_first : minus_first",
-                               "(r2 & 0u) ? plus_first : minus_first"),
+    "lem_side_order_ignored": ("(r2 & 1u) ? plus_first : minus_first;\n  int ranked[7];",
+                               "(r2 & 0u) ? plus_first : minus_first;\n  int ranked[7];"),
     "lem_threshold_index_dropped": ("if (r1 >= lem_threshold[i]) index += 1;",
-                                    "if (r1 >= lem_threshold[0]) index += 1;"),
+                                    "if (r1 >= lem_threshold[0]) index += 1;", 0),
     "aco_weights_swapped": ("eta[0] = eta[1] = heuristic_weight(D2_DIAGONAL, p->beta);",
                             "eta[0] = eta[1] = heuristic_weight(D2_LATERAL, p->beta);"),
-    "aco_uses_r2": ("u = (float)(r1 >> 8) * 0x1p-24f;", "u = (float)(r2 >> 8) * 0x1p-24f;"),
-    "aco_alpha_ignored": ("for (a = 1; a < alpha; ++a)", "for (a = 1; a < 1; ++a)"),
+    "aco_uses_r2": ("u = (float)(r1 >> 8) * 0x1p-24f;", "u = (float)(r2 >> 8) * 0x1p-24f;", 0),
+    "aco_alpha_ignored": ("if (avail[i]) {\n      float power = 1.0f;\n      int a;\n      if (alpha > 0) {\n"
+                          "        power = tau[i];\n        for (a = 1; a < alpha; ++a)",
+                          "if (avail[i]) {\n      float power = 1.0f;\n      int a;\n      if (alpha > 0) {\n"
+                          "        power = tau[i];\n        for (a = 1; a < 1; ++a)"),
     "deposit_before_evaporation": ("float va = keep * tau_a[c];",
-                                   "float va = keep * (tau_a[c] + (code[c] == O_A ? p->dtau : 0.0f));"),
-    "winner_highest_ticket": ("w[0] < best_ticket ||", "w[0] > best_ticket ||"),
+                                   "float va = keep * (tau_a[c] + (code[c] == O_A ? p->dtau : 0.0f));", 0),
+    "winner_highest_ticket": ("w[0] < best_ticket || (w[0] == best_ticket && k < best_k)",
+                              "w[0] > best_ticket || (w[0] == best_ticket && k < best_k)"),
     "source_id_not_cleared": ("new_id[n] = 0;", "(void)0;"),
     "diagonal_sign_flipped": ("case O_REQ_FDP: *tx = x + d; *ty = y + 1; break;",
                               "case O_REQ_FDP: *tx = x + d; *ty = y - 1; break;"),
     "b_heads_plus_x": ("return group == O_A ? 1 : -1;", "return 1;"),
     "forward_first_dropped": ("if (free_cell(p, code, x + d, y)) return O_REQ_F;", ""),
-    "other_groups_pheromone": ("(g == O_A) ? tau_a : tau_b", "(g == O_A) ? tau_b : tau_a"),
+    "other_groups_pheromone": ("(g == O_A) ? tau_a : tau_b", "(g == O_A) ? tau_b : tau_a", 0),
     "tour_diagonal_counts_one": ("(best_dx != 0 && best_dy != 0) ? diagonal_step : 1.0f", "1.0f"),
     "tour_deposit_on_occupied": ("if (entered[c] == O_A) evaporated_a",
                                  "if (code[c] == O_A) evaporated_a"),
@@ -82,6 +86,18 @@ MUTANTS = {
                                 "      if (0) {\n        choice = 0; /* forward first */"),
     "range_gather_radius_one": ("for (dy = -M; dy <= M; ++dy)\n        for (dx = -M; dx <= M; ++dx) {",
                                 "for (dy = -1; dy <= 1; ++dy)\n        for (dx = -1; dx <= 1; ++dx) {"),
+    "range_side_order_ignored": ("(r2 & 1u) ? plus_first : minus_first;\n  int ranked[4];",
+                                 "(r2 & 0u) ? plus_first : minus_first;\n  int ranked[4];"),
+    "range_aco_alpha_ignored": ("if (f[i] >= 1) {\n      float power = 1.0f;\n      int a;\n      if (alpha > 0) {\n"
+                                "        power = tau[i];\n        for (a = 1; a < alpha; ++a)",
+                                "if (f[i] >= 1) {\n      float power = 1.0f;\n      int a;\n      if (alpha > 0) {\n"
+                                "        power = tau[i];\n        for (a = 1; a < 1; ++a)"),
+    "range_deposit_before_evaporation": ("float va = keep * tau_a[c];",
+                                         "float va = keep * (tau_a[c] + (code[c] == O_A ? p->dtau : 0.0f));", 1),
+    "range_aco_uses_r2": ("u = (float)(r1 >> 8) * 0x1p-24f;", "u = (float)(r2 >> 8) * 0x1p-24f;", 1),
+    "range_threshold_index_dropped": ("if (r1 >= lem_threshold[i]) index += 1;",
+                                      "if (r1 >= lem_threshold[0]) index += 1;", 1),
+    "range_other_groups_pheromone": ("(g == O_A) ? tau_a : tau_b", "(g == O_A) ? tau_b : tau_a", 1),
     "range_winner_highest_ticket": ("if (!have || w[0] < best_ticket || (w[0] == best_ticket && kk < best_k)) {",
                                     "if (!have || w[0] > best_ticket || (w[0] == best_ticket && kk < best_k)) {"),
 }
@@ -90,15 +106,23 @@ MUTANTS = {
 @pytest.mark.slow
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_planted_mistake_fails_a_pin(name):
-    old, new = MUTANTS[name]
+    old, new = MUTANTS[name][:2]
+    nth = MUTANTS[name][2] if len(MUTANTS[name]) > 2 else None
     with open(SRC) as f:
         src = f.read()
-    assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+    if nth is None:
+        assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+        nth = 0
+    # the base model and the range model share some lines: nth picks which copy
+    assert src.count(old) > nth, f"mutation anchor for {name} missing"
+    at = -1
+    for _ in range(nth + 1):
+        at = src.index(old, at + 1)
     with tempfile.TemporaryDirectory() as d:
         msrc = os.path.join(d, "mutant.c")
         mlib = os.path.join(d, "libmutant.so")
         with open(msrc, "w") as f:
-            f.write(src.replace(old, new))
+            f.write(src[:at] + new + src[at + len(old):])
         subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
                         "-o", mlib, msrc, "-lm"], check=True)
         env = dict(os.environ, PEDSIM_ORACLE_LIB=mlib)
