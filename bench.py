@@ -33,12 +33,16 @@ WORKLOADS = {
                           "50,000 agents per group (100K), 2,000 steps"),
     "aco_nb8_1024x512": ("aco_nb8_1024x512", "ACO with all eight neighbours as candidates 1024x512, "
                          "50,000 agents per group (100K), 2,000 steps"),
+    "aco_range_1024x512": ("range_1024x512", "ACO 1024x512, 50,000 agents per group (100K), scanning range 4, "
+                           "moving range 2, 2,000 steps"),
+    "lem_range_1024x512": ("range_1024x512", "LEM 1024x512, 50,000 agents per group (100K), scanning range 4, "
+                           "moving range 2, 2,000 steps"),
     "stress_aco_4096x2048": ("stress_4096x2048", "ACO 4096x2048, 5% obstacles, 1M agents"),
     "stress_lem_4096x2048": ("stress_4096x2048", "LEM 4096x2048, 5% obstacles, 1M agents"),
 }
 # workloads run by the single-scenario path
 PLAIN = ("aco_1024x512", "aco_tour_1024x512", "aco_nb8_1024x512", "lem_200x100", "stress_aco_4096x2048",
-         "stress_lem_4096x2048")
+         "stress_lem_4096x2048", "aco_range_1024x512", "lem_range_1024x512")
 MODE_NAMES = {0: "LEM", 1: "ACO", 2: "ACO tour variant"}
 
 
@@ -50,6 +54,8 @@ def make(workload):
     from paper_1412_4933_amd import scenarios as S
     if workload == "stress_lem_4096x2048":
         return S.stress_4096x2048(S.MODE_LEM)
+    if workload == "lem_range_1024x512":
+        return S.range_1024x512(S.MODE_LEM)
     return getattr(S, WORKLOADS[workload][0])()
 
 
@@ -62,13 +68,22 @@ def algorithmic_bytes_per_step(mode: int, cells: int, agents: int) -> int:
     return cells * (1 + (16 if mode != 0 else 0)) + agents * (4 + (8 if mode == 2 else 0))
 
 
-def kernel_source_digest() -> str:
+# The sources that define each traced kernel's device code.
+KERNEL_SOURCES = {
+    "tile_rows_kernel": ("tile_rows.hpp", "tile_engine.hpp", "rules.hpp"),
+    "tile_kernel": ("tile_engine.hpp", "rules.hpp"),
+    "range_kernel": ("range_step.hip", "range_step.hpp", "rules.hpp"),
+}
+
+
+def kernel_source_digest(kernel: str = "") -> str:
+    """Digest of the sources of `kernel` (all kernel sources if unknown)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1412_4933_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    names = KERNEL_SOURCES.get(kernel) or tuple(n for n in os.listdir(csrc) if n.endswith((".hip", ".hpp")))
+    for name in sorted(names):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
 
 
@@ -80,7 +95,7 @@ def measured_traffic(workload: str, kernel: str, tiling=None):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_src_digest") != kernel_source_digest():
+    if rec.get("kernel_src_digest") != kernel_source_digest(kernel):
         return None
     if tiling is not None and rec.get("tiling") is not None and list(rec["tiling"]) != list(tiling):
         return None
@@ -240,6 +255,51 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes_per_dispatch": n * 4, "dispatches": 4}), flush=True)
 
 
+def _counter_per_dispatch(run_dir: str, kernel: str, counter: str):
+    """Mean value of `counter` per dispatch of kernels whose name contains
+    `kernel`, from a rocprofv3 --pmc run's CSV output (summed over the rows of
+    one dispatch), and the number of dispatches."""
+    import csv
+    import glob
+    per = {}
+    for path in glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(path, newline="") as f:
+            for row in csv.DictReader(f):
+                if kernel not in row.get("Kernel_Name", "") or row.get("Counter_Name") != counter:
+                    continue
+                key = (path, row.get("Dispatch_Id") or row.get("Correlation_Id"))
+                per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+    if not per:
+        raise SystemExit(f"no {counter} rows for {kernel} under {run_dir}")
+    return sum(per.values()) / len(per), len(per)
+
+
+def record_traffic(kernel: str, workload: str, fetch_dir: str, write_dir: str, copy_fetch_dir: str,
+                   copy_write_dir: str, tiling: str, steps_per_launch: int) -> None:
+    """Write profiles/traffic_<kernel>_<workload>.json from four rocprofv3
+    --pmc runs (FETCH_SIZE and WRITE_SIZE of the kernel, and of the 1 GiB copy
+    of --calibrate-copy, which scales each counter to bytes)."""
+    copy_bytes = 1 << 30
+    cf, _ = _counter_per_dispatch(copy_fetch_dir, "copyBuffer", "FETCH_SIZE")
+    cw, _ = _counter_per_dispatch(copy_write_dir, "copyBuffer", "WRITE_SIZE")
+    fetch_scale = copy_bytes / 1024.0 / cf
+    write_scale = copy_bytes / 1024.0 / cw
+    kf, nf = _counter_per_dispatch(fetch_dir, kernel, "FETCH_SIZE")
+    kw, nw = _counter_per_dispatch(write_dir, kernel, "WRITE_SIZE")
+    rec = {"kernel": kernel, "workload": workload, "kernel_src_digest": kernel_source_digest(kernel),
+           "tiling": [int(v) for v in tiling.split(",")], "steps_per_launch": steps_per_launch,
+           "fetch_kib_per_dispatch": round(kf, 1), "write_kib_per_dispatch": round(kw, 1),
+           "dispatches": [nf, nw],
+           "copy_fetch_kib": round(cf, 1), "copy_write_kib": round(cw, 1),
+           "fetch_scale": round(fetch_scale, 4), "write_scale": round(write_scale, 4),
+           "bytes_per_launch": int(round((kf * fetch_scale + kw * write_scale) * 1024))}
+    out = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print(json.dumps(rec), flush=True)
+
+
 def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 8) -> float:
     """Achievable HBM bandwidth on this machine: a plain device-to-device copy of
     nbytes (read nbytes + write nbytes per copy), best of `reps`, in GB/s."""
@@ -284,7 +344,15 @@ def main():
                     help="nw,rows,steps_per_launch,threads for the step kernel (default: the library's)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration for profiles)")
+    ap.add_argument("--record-traffic", nargs=8,
+                    metavar=("KERNEL", "WORKLOAD", "FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR",
+                             "TILING", "STEPS_PER_LAUNCH"),
+                    help="write profiles/traffic_<kernel>_<workload>.json from rocprofv3 --pmc runs "
+                         "(no GPU work)")
     args = ap.parse_args()
+    if args.record_traffic:
+        k, w, fd, wd, cfd, cwd, tl, spl = args.record_traffic
+        return record_traffic(k, w, fd, wd, cfd, cwd, tl, int(spl))
     if args.calibrate_copy:
         return calibrate_copy()
     if args.gpus != 1:
@@ -332,7 +400,10 @@ def main():
     def make_sim():
         sim = pedsim.Sim(scn, stream=stream)
         if tiling_arg is not None:
-            sim.set_tiling(mode, *tiling_arg)
+            if getattr(scn, "ranges", None) is not None:  # cols,rows,1,threads for the range kernel
+                sim.set_range_tiling(tiling_arg[0], tiling_arg[1], tiling_arg[3])
+            else:
+                sim.set_tiling(mode, *tiling_arg)
         return sim
 
     if args.warmup > 0:
@@ -376,9 +447,16 @@ def main():
 
     # per-launch durations of the step kernel with HIP events on the launch stream
     prof = make_sim()
-    tiling = pedsim.sim_get_tiling(prof.h, mode)
-    tiling_source = ("--tiling" if tiling_arg is not None
-                     else "autotuner cache" if mode in prof.tuned else "library default")
+    ranged = getattr(scn, "ranges", None) is not None
+    if ranged:  # range kernel: one step per launch, tiles of cols x rows cells
+        cols, rows, threads = pedsim.sim_get_range_tiling(prof.h)
+        tiling = (cols, rows, 1, threads)
+        tiling_source = ("--tiling" if tiling_arg is not None else "library default") + \
+            " (range kernel: cols, rows, steps per launch, threads)"
+    else:
+        tiling = pedsim.sim_get_tiling(prof.h, mode)
+        tiling_source = ("--tiling" if tiling_arg is not None
+                         else "autotuner cache" if mode in prof.tuned else "library default")
     per_kernel = pedsim.sim_step_timed(prof.h, mode, K, stream)
     prof.close()
     log("tiling (nw, rows, steps/launch, threads):", tiling)
@@ -387,7 +465,8 @@ def main():
     # `stream`: the step kernel's average duration is the region's event time
     # (minus the copy-back launches, if any) over its launch count.
     dom_n = per_kernel["tile_kernel"][1]
-    dom = "tile_rows_kernel" if tiling[0] in (0, 3) else "tile_kernel"  # kernel symbol in traces
+    dom = ("range_kernel" if ranged else
+           "tile_rows_kernel" if tiling[0] in (0, 3) else "tile_kernel")  # kernel symbol in traces
     copy_ms = per_kernel["copy_back"][0]
     dom_avg_ms = (ms - copy_ms) / dom_n
     alg_step = algorithmic_bytes_per_step(mode, cells, agents)
@@ -426,6 +505,7 @@ def main():
         "config": {"workload": WORKLOADS[args.workload][1], "grid": f"{scn.W}x{scn.H}",
                    "agents": agents, "mode": MODE_NAMES[mode], "seed": scn.seed,
                    "neighbours": getattr(scn, "neighbours", 5),
+                   "ranges": list(scn.ranges) if getattr(scn, "ranges", None) else None,
                    "timed_steps": f"steps 0..{K - 1} of the workload's {scn.steps}, from its initial state",
                    "tiling": list(tiling), "tiling_source": tiling_source},
         "roofline": roofline,

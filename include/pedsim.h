@@ -164,6 +164,53 @@ int sim_step_aco_tour(sim_handle* h, int32_t nsteps, void* stream);
  */
 int sim_set_neighbours(sim_handle* h, int32_t n);
 
+/*
+ * Larger scanning and moving ranges (the paper's future work, Sec. VII, which
+ * names them without a rule; the rule below widens Sec. III and IV.b-d).
+ * Every later sim_step_lem / sim_step_aco on h uses a scanning range
+ * `scan` and a moving range `move`, 1 <= move <= scan <= 8:
+ *   - the candidates F, FD-, FD+, L-, L+ become rays; along each ray the
+ *     agent sees its free run f, the number of consecutive cells next to it
+ *     that are inside the grid and empty at the start of the step, at most
+ *     `scan`; a ray with f >= 1 is open and is travelled k = min(f, move)
+ *     cells; paths may cross, only landing cells are contested;
+ *   - an open forward ray is taken without a draw. Otherwise LEM (eq. 1)
+ *     scores an open side ray by (f/scan)(Dmin/D), where D is the distance
+ *     from its landing cell to the point move+1 cells ahead of the agent
+ *     (D^2 = (move+1 - a k)^2 + k^2, a = 1 for a diagonal, 0 for a lateral),
+ *     ranks the open side rays by score, highest first, ties in the order
+ *     [FD_s, FD_-s, L_s, L_-s], and takes the rank index of the normal draw
+ *     of the base rule. ACO (eq. 2) weighs an open side ray by
+ *     tau_g(landing cell)^alpha * eta, eta = the float nearest to
+ *     (f/scan)^beta D^-beta (sim_range_weights), with the base rule's
+ *     roulette, order and all-zero fallback;
+ *   - every cell empty at the start of the step goes to the lowest
+ *     (Philox word 0, agent number) among the agents landing on it; then
+ *     eq. 3 and eq. 4 on every cell, as in the base step.
+ * With scan = move = 1 every rule is the base step's, and the results are
+ * identical to it. scan = move = 0 returns h to the base step. One launch
+ * per step (its dependence reaches 2*move + scan cells, so several steps
+ * per launch would need a wide halo). SIM_EINVAL for other values, on a
+ * handle with the eight-neighbour set, and for sim_step_aco_tour while
+ * ranges are set (not combined).
+ */
+int sim_set_ranges(sim_handle* h, int32_t scan, int32_t move);
+
+/* Launch shape of the range step (results never depend on it): tile
+ * interiors of cols (16..256) x rows (8..256) cells, `threads` per workgroup
+ * (multiple of 64, <= 512); the workgroup keeps the codes of the interior
+ * plus a (2*move + scan)-cell halo, 64-bit claim keys of the interior plus a
+ * move-cell halo, and a byte per interior cell in LDS. SIM_EINVAL if ranges
+ * are not set or the shape does not fit. sim_get_range_tiling writes
+ * {cols, rows, threads}. */
+int sim_set_range_tiling(sim_handle* h, int32_t cols, int32_t rows, int32_t threads);
+int sim_get_range_tiling(sim_handle* h, int32_t out[3]);
+
+/* Host-only: the ACO heuristic weights eta of sim_set_ranges for free runs
+ * f = 1..8 (entry f-1; 0 for f > scan): diagonal[] for FD rays, lateral[]
+ * for L rays. SIM_EINVAL for ranges or beta (0..8) out of bounds. */
+int sim_range_weights(int32_t scan, int32_t move, int32_t beta, float diagonal[8], float lateral[8]);
+
 /* Counters after the last completed step; synchronises `stream`. */
 int sim_stats(sim_handle* h, sim_stats_t* out, void* stream);
 

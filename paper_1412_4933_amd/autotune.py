@@ -49,6 +49,14 @@ BATCH_CANDIDATES = [
     (3, 62, 3, 256, 4),
 ]
 
+# (cols, rows, threads) of the range kernel (larger scanning and moving
+# ranges, one step per launch)
+RANGE_CANDIDATES = [
+    (64, 16, 256), (64, 24, 256), (64, 32, 256), (64, 48, 256), (64, 64, 256), (64, 32, 512),
+    (64, 64, 512), (128, 16, 256), (128, 32, 256), (128, 32, 512), (32, 32, 256), (32, 16, 128),
+    (48, 32, 256), (96, 32, 256),
+]
+
 _cache: Dict[str, tuple] = {}
 _loaded = False
 
@@ -62,7 +70,9 @@ def signature(scns: Sequence, kind: str) -> str:
     aco = sum(1 for s in scns if s.mode != 0)
     tour = sum(1 for s in scns if s.mode == 2)
     nb = max(getattr(s, "neighbours", 5) for s in scns)
-    return f"{kind}:n{len(scns)}:c{_bucket(cells)}:a{_bucket(aco + 1)}:t{_bucket(tour + 1)}:nb{nb}"
+    key = f"{kind}:n{len(scns)}:c{_bucket(cells)}:a{_bucket(aco + 1)}:t{_bucket(tour + 1)}:nb{nb}"
+    ranges = getattr(scns[0], "ranges", None) if len(scns) == 1 else None
+    return key + (f":r{ranges[0]}x{ranges[1]}" if ranges else "")
 
 
 def load(path: Optional[str] = None) -> None:
@@ -100,6 +110,14 @@ def cached_batch(scns: Sequence) -> Optional[tuple]:
     return _cache.get(signature(scns, "batch")) if scns else None
 
 
+def cached_range(scn, mode: int) -> Optional[tuple]:
+    """The cached (cols, rows, threads) of the range kernel for `scn`, if any."""
+    _ensure_loaded()
+    if getattr(scn, "ranges", None) is None:
+        return None
+    return _cache.get(signature([scn], f"range{mode}"))
+
+
 def _timed(fn) -> float:
     import torch
     torch.cuda.synchronize()
@@ -128,6 +146,33 @@ def tune_plain(scn, mode: int, steps: Optional[int] = None, candidates: Iterable
         warm.close()
         sim = pedsim.Sim(scn, device=device, autotune=False)
         sim.set_tiling(mode, *tl)
+        dt = _timed(lambda: sim.step(steps, mode))
+        sim.close()
+        timings.append((dt, tuple(tl)))
+    timings.sort()
+    _cache[key] = timings[0][1]
+    return timings[0][1], timings
+
+
+def tune_range(scn, mode: int, steps: Optional[int] = None, candidates: Iterable = RANGE_CANDIDATES,
+               device: str = "cuda") -> Tuple[tuple, List[tuple]]:
+    """Fastest range-kernel tiling (cols, rows, threads) for one scenario with
+    ranges, each candidate timed over the same `steps` from the initial
+    state. Returns (best, [(seconds, tiling)]) and caches best."""
+    steps = steps or scn.steps or 100
+    key = signature([scn], f"range{mode}")
+    timings = []
+    for tl in candidates:
+        warm = pedsim.Sim(scn, device=device, autotune=False)
+        try:
+            warm.set_range_tiling(*tl)
+        except pedsim.SimError:
+            warm.close()
+            continue
+        warm.step(1, mode)  # loads the kernel
+        warm.close()
+        sim = pedsim.Sim(scn, device=device, autotune=False)
+        sim.set_range_tiling(*tl)
         dt = _timed(lambda: sim.step(steps, mode))
         sim.close()
         timings.append((dt, tuple(tl)))
@@ -193,6 +238,8 @@ def _workloads():
         "aco_nb8_1024x512": ("plain", S.aco_nb8_1024x512, S.MODE_ACO),
         "stress_aco_4096x2048": ("plain", lambda: S.stress_4096x2048(S.MODE_ACO), S.MODE_ACO),
         "stress_lem_4096x2048": ("plain", lambda: S.stress_4096x2048(S.MODE_LEM), S.MODE_LEM),
+        "aco_range_1024x512": ("range", lambda: S.range_1024x512(S.MODE_ACO), S.MODE_ACO),
+        "lem_range_1024x512": ("range", lambda: S.range_1024x512(S.MODE_LEM), S.MODE_LEM),
         "batched_256": ("batch", S.batched_256, None),
     }
 
@@ -211,6 +258,9 @@ def main(argv=None) -> int:
         if kind == "plain":
             scn = build()
             best, timings = tune_plain(scn, mode, args.steps)
+        elif kind == "range":
+            scn = build()
+            best, timings = tune_range(scn, mode, args.steps)
         else:
             scns = build()
             best, timings = tune_batch(scns, args.steps)

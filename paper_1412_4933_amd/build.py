@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpedsim.so")
 
-SOURCES = ["step_plain.hip", "step_batch.hip", "pedsim_capi.hip", "batch_capi.hip"]
+SOURCES = ["step_plain.hip", "step_batch.hip", "range_step.hip", "pedsim_capi.hip", "batch_capi.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -401,7 +401,7 @@ int sim_batch_attach_tour(sim_batch* b, int32_t slot, float* d_tour, float* d_to
     hipStream_t s = (hipStream_t)stream;
     unsigned long long* counters = x.totals + kTileStatFields;
     unsigned long long host_counters[3];
-    PEDSIM_HIP(hipMemsetAsync(counters, 0, 3 * sizeof(unsigned long long), s));
+    PEDSIM_HIP(launch_zero_words(counters, 3 * sizeof(unsigned long long) / 4, s));
     PEDSIM_HIP(launch_validate_values(d_tour, (size_t)x.agents, counters, s));
     PEDSIM_HIP(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s));
     PEDSIM_HIP(hipStreamSynchronize(s));

@@ -14,6 +14,7 @@
 
 #include "pedsim.h"
 #include "pedsim_internal.hpp"
+#include "range_step.hpp"
 
 namespace pedsim {
 
@@ -97,7 +98,7 @@ int validate_state(const sim_params* p, const uint8_t* d_code, const uint32_t* d
   const size_t cells = (size_t)p->W * (size_t)p->H;
   unsigned long long* counters = (unsigned long long*)(scratch + L.totals) + kTileStatFields;
   unsigned long long host_counters[3];
-  PEDSIM_HIP(hipMemsetAsync(counters, 0, 3 * sizeof(unsigned long long), s));
+  PEDSIM_HIP(launch_zero_words(counters, 3 * sizeof(unsigned long long) / 4, s));
   PEDSIM_HIP(launch_validate(d_code, d_id, d_tau, cells, counters, s));
   PEDSIM_HIP(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s));
   PEDSIM_HIP(hipStreamSynchronize(s));
@@ -106,7 +107,7 @@ int validate_state(const sim_params* p, const uint8_t* d_code, const uint32_t* d
   if (agents) *agents = n;
   if (n > 0) {
     uint32_t* bitmap = (uint32_t*)(scratch + L.id2);
-    PEDSIM_HIP(hipMemsetAsync(bitmap, 0, (n + 31) / 32 * sizeof(uint32_t), s));
+    PEDSIM_HIP(launch_zero_words(bitmap, (n + 31) / 32, s));
     PEDSIM_HIP(launch_validate_ids(d_id, cells, (uint32_t)n, bitmap, counters, s));
     PEDSIM_HIP(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s));
     PEDSIM_HIP(hipStreamSynchronize(s));
@@ -166,6 +167,12 @@ struct sim_handle {
   Tiling tiling[3];
   uint64_t t;      // index of the next step
   uint64_t agents; // number of agents (ids 1..agents)
+  // Larger scanning and moving ranges: scan = 0 runs the base engines;
+  // otherwise LEM and ACO steps run the range kernel with these ranges on
+  // tiles of range_cols x range_rows cells, range_threads per workgroup.
+  int scan, move;
+  int range_cols, range_rows, range_threads;
+  float range_eta[2][kRangeMax];
 };
 
 namespace {
@@ -199,12 +206,119 @@ int plan(int nsteps, int per, int* chunks, int cap) {
   return n;
 }
 
+// eta^beta of a side ray with ranges (S, M): the float nearest to
+// (f/S)^beta D2^(-beta/2), D2 the squared distance from the landing cell
+// (k = min(f, M) cells along the ray; a = 1 for a diagonal, 0 for a lateral)
+// to the point M+1 cells ahead. Evaluated in long double, then rounded once.
+static float range_eta(int a, int f, int S, int M, int beta) {
+  const int k = f < M ? f : M;
+  const long double dx = (long double)(M + 1 - a * k);
+  const long double d2 = dx * dx + (long double)k * (long double)k;
+  const long double v = powl((long double)f / (long double)S, (long double)beta) * powl(d2, -0.5L * (long double)beta);
+  return (float)v;
+}
+
+static void fill_range_eta(int S, int M, int beta, float out[2][kRangeMax]) {
+  for (int f = 1; f <= kRangeMax; ++f) {
+    out[0][f - 1] = f <= S ? range_eta(0, f, S, M, beta) : 0.0f;
+    out[1][f - 1] = f <= S ? range_eta(1, f, S, M, beta) : 0.0f;
+  }
+}
+
+// Range tiling is valid when the interior is at least 16 x 8 (bounds the
+// per-tile counters) and the workgroup's LDS fits.
+static bool range_tiling_valid(int cols, int rows, int threads, int S, int M) {
+  if (cols < kMinInteriorX || cols > 256 || rows < kMinInteriorY || rows > 256) return false;
+  if (threads < 64 || threads > kRangeMaxThreads || threads % 64) return false;
+  return RangeLayout{cols, rows, S, M, true}.bytes() <= (size_t)max_dynamic_lds();
+}
+
+// Default range tiling: 64 x 32 interiors (shorter where the LDS of long
+// ranges does not fit), 512 threads per workgroup.
+static bool default_range_tiling(sim_handle* h) {
+  static const int shapes[][2] = {{64, 32}, {64, 16}, {64, 8}, {32, 16}, {32, 8}, {16, 8}};
+  for (const auto& sh : shapes)
+    if (range_tiling_valid(sh[0], sh[1], 512, h->scan, h->move)) {
+      h->range_cols = sh[0];
+      h->range_rows = sh[1];
+      h->range_threads = 512;
+      return true;
+    }
+  return false;
+}
+
+// One range launch per step, ping-ponging between the caller's planes and
+// the shadow copy like the tile engines.
+int run_range_steps(sim_handle* h, int mode, int32_t nsteps, hipStream_t s, hipEvent_t* ev, double* ms,
+                    int64_t* launches) {
+  const size_t cells = (size_t)h->p.W * (size_t)h->p.H;
+  const bool aco = mode != kModeLem;
+  RangeScenario P;
+  memset(&P, 0, sizeof(P));
+  P.W = h->p.W;
+  P.H = h->p.H;
+  P.TX = h->range_cols;
+  P.TY = h->range_rows;
+  P.tiles_x = (P.W + P.TX - 1) / P.TX;
+  P.tiles_y = (P.H + P.TY - 1) / P.TY;
+  P.S = h->scan;
+  P.M = h->move;
+  P.key0 = h->base.key0;
+  P.key1 = h->base.key1;
+  P.keep = h->base.keep;
+  P.dtau = h->base.dtau;
+  P.alpha = h->base.alpha;
+  P.cross_a = h->base.cross_a;
+  P.cross_b = h->base.cross_b;
+  P.tile_stats = h->stats;
+  memcpy(P.eta, h->range_eta, sizeof(P.eta));
+  Planes src = h->user, dst = h->shadow;
+  for (int32_t j = 0; j < nsteps; ++j) {
+    P.code_in = src.code;
+    P.id_in = src.id;
+    P.tau_in = aco ? src.tau : nullptr;
+    P.code_out = dst.code;
+    P.id_out = dst.id;
+    P.tau_out = aco ? dst.tau : nullptr;
+    P.t = h->t;
+    if (ev) (void)hipEventRecord(ev[0], s);
+    PEDSIM_HIP(launch_range(P, mode, h->range_threads, j == nsteps - 1, s));
+    if (ev) {
+      (void)hipEventRecord(ev[1], s);
+      PEDSIM_HIP(hipEventSynchronize(ev[1]));
+      float f = 0.0f;
+      (void)hipEventElapsedTime(&f, ev[0], ev[1]);
+      ms[0] += f;
+      launches[0] += 1;
+    }
+    h->t += 1;
+    const Planes tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+  if (src.code != h->user.code) {  // odd number of launches: state is in the shadow planes
+    if (ev) (void)hipEventRecord(ev[0], s);
+    PEDSIM_HIP(copy_planes(h->user, src, cells, aco, 0, s));
+    if (ev) {
+      (void)hipEventRecord(ev[1], s);
+      PEDSIM_HIP(hipEventSynchronize(ev[1]));
+      float f = 0.0f;
+      (void)hipEventElapsedTime(&f, ev[0], ev[1]);
+      ms[1] += f;
+      launches[1] += 1;
+    }
+  }
+  h->stats_entries = P.tiles_x * P.tiles_y;
+  return SIM_OK;
+}
+
 // Run nsteps steps; ev (optional, 2 events) brackets each tile launch, and
 // its elapsed time is added into ms[0] (launches[0]); a copy-back is timed
 // into ms[1] (launches[1]).
 int run_steps(sim_handle* h, int mode, int32_t nsteps, hipStream_t s, hipEvent_t* ev, double* ms,
               int64_t* launches) {
   if (nsteps == 0) return SIM_OK;
+  if (h->scan) return run_range_steps(h, mode, nsteps, s, ev, ms, launches);
   const Tiling& tl = h->tiling[mode];
   Scenario S = h->base;
   set_geometry(S, tl);
@@ -285,6 +399,9 @@ int init_handle(sim_handle* h, const sim_params* p, uint8_t* d_code, uint32_t* d
   h->tiling[kModeLem] = default_tiling(kModeLem, cells);
   h->tiling[kModeAco] = default_tiling(kModeAco, cells);
   h->tiling[kModeAcoTour] = default_tiling(kModeAcoTour, cells);
+  h->scan = h->move = 0;
+  h->range_cols = h->range_rows = h->range_threads = 0;
+  memset(h->range_eta, 0, sizeof(h->range_eta));
   PEDSIM_HIP(launch_count(d_code, p->W, p->H, p->cross_a, p->cross_b, h->stats, &h->stats_entries, s));
   PEDSIM_HIP(hipStreamSynchronize(s));
   return SIM_OK;
@@ -340,6 +457,7 @@ static int mode_ready(sim_handle* h, int mode) {
   if (mode != kModeLem && mode != kModeAco && mode != kModeAcoTour) return SIM_EINVAL;
   if (mode != kModeLem && !h->user.tau) return SIM_ENOTAU;
   if (mode == kModeAcoTour && h->agents > 0 && !h->user.tour) return SIM_ENOTOUR;
+  if (mode == kModeAcoTour && h->scan) return SIM_EINVAL;  // ranges are not combined with the tour variant
   return SIM_OK;
 }
 
@@ -365,7 +483,7 @@ int sim_attach_tour(sim_handle* h, float* d_tour, float* d_tour_shadow, void* st
     hipStream_t s = (hipStream_t)stream;
     unsigned long long* counters = h->totals + kTileStatFields;
     unsigned long long host_counters[3];
-    PEDSIM_HIP(hipMemsetAsync(counters, 0, 3 * sizeof(unsigned long long), s));
+    PEDSIM_HIP(launch_zero_words(counters, 3 * sizeof(unsigned long long) / 4, s));
     PEDSIM_HIP(launch_validate_values(d_tour, (size_t)h->agents, counters, s));
     PEDSIM_HIP(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s));
     PEDSIM_HIP(hipStreamSynchronize(s));
@@ -378,9 +496,59 @@ int sim_attach_tour(sim_handle* h, float* d_tour, float* d_tour_shadow, void* st
 
 int sim_set_neighbours(sim_handle* h, int32_t n) {
   if (!h || (n != 5 && n != 8)) return SIM_EINVAL;
+  if (n == 8 && h->scan) return SIM_EINVAL;  // ranges are not combined with the eight-neighbour set
   h->base.neighbours = n;
   const size_t cells = (size_t)h->p.W * (size_t)h->p.H;
   for (int m = 0; m < 3; ++m) h->tiling[m] = default_tiling(m, cells, n == 8);
+  return SIM_OK;
+}
+
+int sim_set_ranges(sim_handle* h, int32_t scan, int32_t move) {
+  if (!h) return SIM_EINVAL;
+  if (scan == 0 && move == 0) {
+    h->scan = h->move = 0;
+    return SIM_OK;
+  }
+  if (scan < 1 || scan > kRangeMax || move < 1 || move > scan) return SIM_EINVAL;
+  if (h->base.neighbours == 8) return SIM_EINVAL;
+  const int old_scan = h->scan, old_move = h->move;
+  h->scan = scan;
+  h->move = move;
+  if (!default_range_tiling(h)) {  // no launch shape fits this device's LDS
+    h->scan = old_scan;
+    h->move = old_move;
+    return SIM_EINVAL;
+  }
+  fill_range_eta(scan, move, h->p.beta, h->range_eta);
+  return SIM_OK;
+}
+
+int sim_set_range_tiling(sim_handle* h, int32_t cols, int32_t rows, int32_t threads) {
+  if (!h || !h->scan) return SIM_EINVAL;
+  if (!range_tiling_valid(cols, rows, threads, h->scan, h->move)) return SIM_EINVAL;
+  h->range_cols = cols;
+  h->range_rows = rows;
+  h->range_threads = threads;
+  return SIM_OK;
+}
+
+int sim_get_range_tiling(sim_handle* h, int32_t out[3]) {
+  if (!h || !out || !h->scan) return SIM_EINVAL;
+  out[0] = h->range_cols;
+  out[1] = h->range_rows;
+  out[2] = h->range_threads;
+  return SIM_OK;
+}
+
+int sim_range_weights(int32_t scan, int32_t move, int32_t beta, float diagonal[8], float lateral[8]) {
+  if (scan < 1 || scan > kRangeMax || move < 1 || move > scan || beta < 0 || beta > 8 || !diagonal || !lateral)
+    return SIM_EINVAL;
+  float t[2][kRangeMax];
+  fill_range_eta(scan, move, beta, t);
+  for (int f = 0; f < kRangeMax; ++f) {
+    diagonal[f] = t[1][f];
+    lateral[f] = t[0][f];
+  }
   return SIM_OK;
 }
 

@@ -55,6 +55,8 @@ hipError_t launch_validate(const uint8_t* code, const uint32_t* id, const float*
                            unsigned long long* counters, hipStream_t s);
 hipError_t launch_validate_ids(const uint32_t* id, size_t cells, uint32_t n, uint32_t* bitmap,
                                unsigned long long* counters, hipStream_t s);
+// Zero `words` 32-bit words at p with a kernel.
+hipError_t launch_zero_words(void* p, size_t words, hipStream_t s);
 // counters[2] |= 1 if any of the n values is negative, NaN or infinite.
 hipError_t launch_validate_values(const float* v, size_t n, unsigned long long* counters, hipStream_t s);
 

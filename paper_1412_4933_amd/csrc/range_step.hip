@@ -1,0 +1,400 @@
+// Larger scanning and moving ranges (the paper's future work, Sec. VII) for
+// gfx950: one launch per step, one workgroup per tile.
+//
+// Rules (the base step of Sec. IV.b-d widened to a scanning range S and a
+// moving range M, 1 <= M <= S <= 8):
+//   * the five candidates F, FD-, FD+, L-, L+ become rays; along each ray an
+//     agent sees the free run f (consecutive cells next to it that are inside
+//     the grid and empty at t, at most S); an open ray (f >= 1) is travelled
+//     k = min(f, M) cells;
+//   * forward first: an open forward ray is taken without a draw; otherwise
+//     LEM (eq. 1) ranks the open side rays by (f/S)(Dmin/D), D the distance
+//     from the landing cell to the point M+1 cells ahead, and ACO (eq. 2)
+//     weighs them by tau(landing cell)^alpha (f/S)^beta D^-beta;
+//   * every cell empty at t goes to the lowest (Philox word 0, agent number)
+//     among the agents landing on it; eq. 3 then eq. 4 on every cell.
+// With S = M = 1 this is the base step bit for bit.
+//
+// A tile is an interior of TX x TY cells. The new state of an interior cell
+// depends on the requests of agents up to 2M cells away (the contest at its
+// own cell, or at the target of its agent, up to M away, among requesters up
+// to M from that target), and those requests read cells up to S further out,
+// so the workgroup stages the code plane with a halo of 2M + S. Phases:
+//   1. stage codes (outside the grid counts as wall); clear the claim keys;
+//   2. request: every agent up to 2M from the interior scans its rays in LDS,
+//      chooses, draws its Philox words (the ticket is word 0) and claims its
+//      landing cell with a 64-bit LDS atomic min of
+//      (word 0 << 32 | agent number << 1 | group - 1) -- min is commutative,
+//      so the winner never depends on thread order; landing cells more than
+//      M from the interior are not needed and not claimed;
+//   3. commit + pheromone + counters over the interior: an empty cell with a
+//      claim takes the winner's group and id from its key; an agent whose
+//      landing cell's key names it leaves; both planes evaporate and gain the
+//      deposit where their group stands after the step.
+// Reads one copy of the planes and writes the other (the caller's planes and
+// the scratch shadow ping-pong), since a tile's halo is its neighbours'
+// interior.
+#include "range_step.hpp"
+
+#include "pedsim_internal.hpp"
+
+namespace pedsim {
+
+namespace {
+
+// Ray r (0 F, 1 FD-, 2 FD+, 3 L-, 4 L+) of an agent heading d.
+__device__ __forceinline__ int ray_dx(int r, int d) { return r <= 2 ? d : 0; }
+__device__ __forceinline__ int ray_dy(int r) { return (r == 1 || r == 3) ? -1 : ((r == 2 || r == 4) ? 1 : 0); }
+
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD one
+// contiguous run of row-major tiles so shared halo lines stay in its L2.
+__device__ __forceinline__ int range_tile_of_block(int bid, int ntiles) {
+  const int per = (ntiles + 7) >> 3;
+  return (bid & 7) * per + (bid >> 3);
+}
+
+// LEM over the open side rays 1..4 (f[r] >= 1): a stable sort by descending
+// score C_r = f_r / D_r in the order [FD_s, FD_-s, L_s, L_-s] (s = +1 when
+// bit 0 of w2 is set), then the rank index of the normal draw (as in the base
+// rule), clamped to the last open ray. Returns the ray, or 0 if none is open.
+__device__ __forceinline__ int range_lem(const int f[5], const int d2[5], uint32_t w1, uint32_t w2) {
+  const int flip = (int)(w2 & 1u);
+  int n = 0;
+#pragma unroll
+  for (int r = 1; r <= 4; ++r) n += f[r] >= 1;
+  if (n == 0) return 0;
+  int idx = (w1 >= kNormalCut0) + (w1 >= kNormalCut1) + (w1 >= kNormalCut2);
+  idx = idx < n - 1 ? idx : n - 1;
+  int pick = 0;
+#pragma unroll
+  for (int r = 1; r <= 4; ++r) {
+    if (f[r] < 1) continue;
+    const int pos_r = (r - 1) ^ flip;
+    int rank = 0;
+#pragma unroll
+    for (int q = 1; q <= 4; ++q) {
+      if (q == r || f[q] < 1) continue;
+      // C_q > C_r  <=>  f_q^2 D2_r > f_r^2 D2_q (all small integers)
+      const int lhs = f[q] * f[q] * d2[r];
+      const int rhs = f[r] * f[r] * d2[q];
+      rank += (lhs > rhs) || (lhs == rhs && ((q - 1) ^ flip) < pos_r);
+    }
+    if (rank == idx) pick = r;
+  }
+  return pick;
+}
+
+// ACO over the open side rays: weights tau^alpha * eta summed left to right
+// over FD-, FD+, L-, L+; u = (w1 >> 8) 2^-24; the first ray whose running sum
+// exceeds fl(u * sum), else the last positive one; all-zero weights fall back
+// to the LEM rule with the same words. One binary32 rounding per operation.
+__device__ __forceinline__ int range_aco(const int f[5], const int d2[5], const float tau[5], const float eta[5],
+                                         int alpha, uint32_t w1, uint32_t w2) {
+  float w[5];
+#pragma unroll
+  for (int r = 1; r <= 4; ++r) {
+    float p = 1.0f;
+    if (alpha > 0) {
+      p = tau[r];
+      for (int a = 1; a < alpha; ++a) p = p * tau[r];
+    }
+    w[r] = f[r] >= 1 ? p * eta[r] : 0.0f;
+  }
+  float sum = w[1];
+  sum = sum + w[2];
+  sum = sum + w[3];
+  sum = sum + w[4];
+  if (sum == 0.0f) return range_lem(f, d2, w1, w2);
+  const float u = (float)(w1 >> 8) * 0x1p-24f;
+  const float target = u * sum;
+  float running = 0.0f;
+  int last = 0, pick = 0;
+#pragma unroll
+  for (int r = 1; r <= 4; ++r) {
+    running = running + w[r];
+    if (w[r] > 0.0f) {
+      last = r;
+      if (pick == 0 && target < running) pick = r;
+    }
+  }
+  return pick ? pick : last;
+}
+
+constexpr unsigned long long kNoClaim = ~0ull;
+constexpr int kStageBatch = 8;  // global loads a thread keeps in flight while staging
+
+// q = i / d for i * d < 2^32, with m = ceil(2^32 / d): one multiply-high.
+__device__ __forceinline__ uint32_t div_magic(uint32_t d) {
+  return (uint32_t)((0x100000000ull + d - 1) / d);
+}
+__device__ __forceinline__ int fast_div(int i, uint32_t m) { return (int)__umulhi((uint32_t)i, m); }
+
+template <int MODE>
+__global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P, int last) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int ntiles = P.tiles_x * P.tiles_y;
+  const int tile = range_tile_of_block(blockIdx.x, ntiles);
+  if (tile >= ntiles) return;
+  const int TX = P.TX, TY = P.TY, S = P.S, M = P.M;
+  const int hc = 2 * M + S;  // code halo
+  const int CW = TX + 2 * hc, CH = TY + 2 * hc;
+  const int RW = TX + 4 * M, RH = TY + 4 * M;  // request region: agents up to 2M from the interior
+  const int KW = TX + 2 * M, KH = TY + 2 * M;  // claim keys: cells up to M from the interior
+  const int PW = TX + 6 * M, PH = TY + 6 * M;  // pheromone: cells up to 3M from the interior
+  const RangeLayout L{TX, TY, S, M, MODE != kModeLem};
+  uint8_t* code = smem + L.code();
+  uint32_t* ids = (uint32_t*)(smem + L.ids());
+  unsigned long long* keys = (unsigned long long*)(smem + L.keys());
+  uint8_t* req = smem + L.req();
+  uint32_t* cnt = (uint32_t*)(smem + L.ctl());
+  float* tau_a = (float*)(smem + L.tau());  // ACO: [PH][PW] per plane
+  float* tau_b = tau_a + (size_t)PW * PH;
+
+  const int x0 = (tile % P.tiles_x) * TX, y0 = (tile / P.tiles_x) * TY;
+  const int W = P.W, H = P.H;
+  const int lane = threadIdx.x & 63;
+  const int nthreads = blockDim.x;
+
+  // 1. stage the codes of the region (interior + 2M + S; outside the grid
+  //    reads as wall), the ids of the request region and, for ACO, both
+  //    pheromone planes of the interior + 3M (every landing cell of a
+  //    requester and every interior cell); clear the keys. Each thread keeps
+  //    kStageBatch loads in flight before it writes them to LDS.
+  {
+    const uint32_t mc = div_magic((uint32_t)CW);
+    for (int i0 = threadIdx.x; i0 < CW * CH; i0 += nthreads * kStageBatch) {
+      uint32_t v[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int i = i0 + u * nthreads;
+        const int r = fast_div(i, mc), c = i - r * CW;
+        const int gx = x0 - hc + c, gy = y0 - hc + r;
+        v[u] = (i < CW * CH && gx >= 0 && gx < W && gy >= 0 && gy < H) ? P.code_in[(size_t)gy * W + gx]
+                                                                          : (uint32_t)kWall;
+      }
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u)
+        if (i0 + u * nthreads < CW * CH) code[i0 + u * nthreads] = (uint8_t)v[u];
+    }
+    const uint32_t mr = div_magic((uint32_t)RW);
+    for (int i0 = threadIdx.x; i0 < RW * RH; i0 += nthreads * kStageBatch) {
+      uint32_t v[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int i = i0 + u * nthreads;
+        const int r = fast_div(i, mr), c = i - r * RW;
+        const int gx = x0 - 2 * M + c, gy = y0 - 2 * M + r;
+        v[u] = (i < RW * RH && gx >= 0 && gx < W && gy >= 0 && gy < H) ? P.id_in[(size_t)gy * W + gx] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u)
+        if (i0 + u * nthreads < RW * RH) ids[i0 + u * nthreads] = v[u];
+    }
+    if (MODE != kModeLem) {
+      const size_t plane = (size_t)W * H;
+      const uint32_t mp = div_magic((uint32_t)PW);
+      for (int i0 = threadIdx.x; i0 < PW * PH; i0 += nthreads * kStageBatch) {
+        float va[kStageBatch], vb[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+          const int i = i0 + u * nthreads;
+          const int r = fast_div(i, mp), c = i - r * PW;
+          const int gx = x0 - 3 * M + c, gy = y0 - 3 * M + r;
+          const bool in = i < PW * PH && gx >= 0 && gx < W && gy >= 0 && gy < H;
+          const size_t gi = in ? (size_t)gy * W + gx : 0;
+          va[u] = in ? P.tau_in[gi] : 0.0f;
+          vb[u] = in ? P.tau_in[plane + gi] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+          const int i = i0 + u * nthreads;
+          if (i < PW * PH) {
+            tau_a[i] = va[u];
+            tau_b[i] = vb[u];
+          }
+        }
+      }
+    }
+    for (int i = threadIdx.x; i < KW * KH; i += nthreads) keys[i] = kNoClaim;
+    if (threadIdx.x < 8) cnt[threadIdx.x] = 0u;
+  }
+  __syncthreads();
+
+  // 2. requests of every agent of the request region
+  {
+    const uint32_t mr = div_magic((uint32_t)RW);
+    for (int i = threadIdx.x; i < RW * RH; i += nthreads) {
+      const int r = fast_div(i, mr), c = i - r * RW;
+      const int cx = c + S, cy = r + S;  // code-region coordinates
+      const int g = code[cy * CW + cx];
+      const int ix = c - 2 * M, iy = r - 2 * M;  // interior coordinates
+      const bool interior = ix >= 0 && ix < TX && iy >= 0 && iy < TY;
+      int choice = -1, len = 0;
+      if (g == kGroupA || g == kGroupB) {
+        const int d = g == kGroupA ? 1 : -1;
+        int f[5], d2[5];
+        bool side = false;
+#pragma unroll
+        for (int ray = 0; ray < 5; ++ray) {
+          const int ux = ray_dx(ray, d), uy = ray_dy(ray);
+          // all S cells of the ray read at once (independent LDS loads), the
+          // free run counted afterwards
+          const int step = uy * CW + ux;
+          const int at = cy * CW + cx;
+          uint32_t v[kRangeMax];
+#pragma unroll
+          for (int j = 0; j < kRangeMax; ++j) v[j] = j < S ? code[at + (j + 1) * step] : (uint32_t)kWall;
+          int j = 0;
+          bool open = true;
+#pragma unroll
+          for (int q = 0; q < kRangeMax; ++q) {
+            open = open && v[q] == kEmpty;
+            j += open ? 1 : 0;
+          }
+          f[ray] = j;
+          const int k = j < M ? j : M;
+          const int a = ray <= 2 ? 1 : 0;
+          const int b = ray == 0 ? 0 : 1;
+          const int dx = M + 1 - a * k;
+          d2[ray] = dx * dx + b * k * k;
+          side |= ray > 0 && j >= 1;
+        }
+        if (f[0] >= 1 || side) {
+          const uint32_t k_agent = ids[i] - 1u;
+          const Words w = agent_words(k_agent, P.t, P.key0, P.key1);
+          if (f[0] >= 1) {
+            choice = 0;
+          } else if (MODE == kModeLem) {
+            choice = range_lem(f, d2, w.w1, w.w2);
+          } else {
+            // the agent in pheromone-region coordinates
+            const int px = c + M, py = r + M;
+            const float* tp = g == kGroupA ? tau_a : tau_b;
+            float tau[5], eta[5];
+#pragma unroll
+            for (int ray = 1; ray <= 4; ++ray) {
+              tau[ray] = 0.0f;
+              eta[ray] = 0.0f;
+              if (f[ray] >= 1) {
+                const int k = f[ray] < M ? f[ray] : M;
+                eta[ray] = P.eta[ray <= 2 ? 1 : 0][f[ray] - 1];
+                tau[ray] = tp[(py + k * ray_dy(ray)) * PW + px + k * ray_dx(ray, d)];
+              }
+            }
+            choice = range_aco(f, d2, tau, eta, P.alpha, w.w1, w.w2);
+          }
+          len = f[choice] < M ? f[choice] : M;
+          // landing cell in key-region coordinates; farther ones are not needed
+          const int kx = c - M + len * ray_dx(choice, d);
+          const int ky = r - M + len * ray_dy(choice);
+          if (kx >= 0 && kx < KW && ky >= 0 && ky < KH) {
+            const unsigned long long key = ((unsigned long long)w.w0 << 32) |
+                                           ((unsigned long long)k_agent << 1) | (unsigned long long)(g - 1);
+            atomicMin(&keys[ky * KW + kx], key);
+          }
+        }
+      }
+      if (interior) req[iy * TX + ix] = choice >= 0 ? (uint8_t)((choice + 1) | (len << 3)) : (uint8_t)0;
+    }
+  }
+  __syncthreads();
+
+  // 3. commit, pheromone (eq. 3 then eq. 4) and counters over the interior
+  uint32_t n_a = 0, n_b = 0, c_a = 0, c_b = 0, moved = 0;
+  const size_t plane = (size_t)W * H;
+  {
+    const uint32_t mt = div_magic((uint32_t)TX);
+    for (int i = threadIdx.x; i < TX * TY; i += nthreads) {
+      const int iy = fast_div(i, mt), ix = i - iy * TX;
+      const int gx = x0 + ix, gy = y0 + iy;
+      if (gx >= W || gy >= H) continue;
+      const size_t gi = (size_t)gy * W + gx;
+      const int g0 = code[(iy + hc) * CW + ix + hc];
+      int nc = g0;
+      uint32_t nid = 0u;
+      if (g0 == kEmpty) {
+        const unsigned long long key = keys[(iy + M) * KW + ix + M];
+        if (key != kNoClaim) {
+          nc = (int)(key & 1ull) + 1;
+          nid = (uint32_t)((key >> 1) & 0x7fffffffull) + 1u;
+          moved += 1;
+        }
+      } else if (g0 == kGroupA || g0 == kGroupB) {
+        nid = ids[(iy + 2 * M) * RW + ix + 2 * M];
+        const int rq = req[i];
+        if (rq) {
+          const int ray = (rq & 7) - 1, len = rq >> 3;
+          const int d = g0 == kGroupA ? 1 : -1;
+          const int kx = ix + M + len * ray_dx(ray, d), ky = iy + M + len * ray_dy(ray);
+          const unsigned long long key = keys[ky * KW + kx];
+          if ((uint32_t)((key >> 1) & 0x7fffffffull) == nid - 1u) {
+            nc = kEmpty;
+            nid = 0u;
+          }
+        }
+      }
+      P.code_out[gi] = (uint8_t)nc;
+      P.id_out[gi] = nid;
+      if (MODE != kModeLem) {
+        const int pi = (iy + 3 * M) * PW + ix + 3 * M;
+        float va = P.keep * tau_a[pi];
+        float vb = P.keep * tau_b[pi];
+        if (nc == kGroupA) va = va + P.dtau;
+        if (nc == kGroupB) vb = vb + P.dtau;
+        P.tau_out[gi] = va;
+        P.tau_out[plane + gi] = vb;
+      }
+      n_a += nc == kGroupA;
+      n_b += nc == kGroupB;
+      c_a += nc == kGroupA && gx >= W - P.cross_b;
+      c_b += nc == kGroupB && gx < P.cross_a;
+    }
+  }
+  if (last) {
+    // one LDS atomic per wave after a cross-lane sum
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      n_a += __shfl_xor(n_a, off);
+      n_b += __shfl_xor(n_b, off);
+      c_a += __shfl_xor(c_a, off);
+      c_b += __shfl_xor(c_b, off);
+      moved += __shfl_xor(moved, off);
+    }
+    if (lane == 0) {
+      atomicAdd(&cnt[0], n_a);
+      atomicAdd(&cnt[1], n_b);
+      atomicAdd(&cnt[2], c_a);
+      atomicAdd(&cnt[3], c_b);
+      atomicAdd(&cnt[4], moved);
+    }
+    __syncthreads();
+    if (threadIdx.x < kTileStatFields) P.tile_stats[(size_t)tile * kTileStatFields + threadIdx.x] = cnt[threadIdx.x];
+  }
+}
+
+template <int MODE>
+hipError_t launch_range_mode(const RangeScenario& P, int threads, int last, hipStream_t s) {
+  const size_t lds = RangeLayout{P.TX, P.TY, P.S, P.M, MODE != kModeLem}.bytes();
+  static bool attr_done = false;
+  if (!attr_done) {
+    (void)hipFuncSetAttribute((const void*)range_kernel<MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              max_dynamic_lds());
+    (void)hipGetLastError();  // an unsupported attribute value must not linger as the last error
+    attr_done = true;
+  }
+  const int ntiles = P.tiles_x * P.tiles_y;
+  const int blocks = ((ntiles + 7) / 8) * 8;
+  range_kernel<MODE><<<blocks, threads, lds, s>>>(P, last);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_range(const RangeScenario& P, int mode, int threads, int last, hipStream_t s) {
+  if (threads < 64 || threads > kRangeMaxThreads || threads % 64) return hipErrorInvalidValue;
+  if (P.S < 1 || P.S > kRangeMax || P.M < 1 || P.M > P.S) return hipErrorInvalidValue;
+  return mode == kModeLem ? launch_range_mode<kModeLem>(P, threads, last, s)
+                          : launch_range_mode<kModeAco>(P, threads, last, s);
+}
+
+}  // namespace pedsim

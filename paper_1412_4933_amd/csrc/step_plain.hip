@@ -247,6 +247,20 @@ __global__ __launch_bounds__(256) void validate_values_kernel(const float* v, si
   if (bad) atomicOr(&counters[2], 1ull);
 }
 
+// Clear `words` 32-bit words with stores from a kernel (not a memset node:
+// the calls that clear counters may be recorded into a graph by a caller).
+__global__ __launch_bounds__(256) void zero_words_kernel(uint32_t* p, size_t words) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (size_t)gridDim.x * 256) p[i] = 0u;
+}
+
+hipError_t launch_zero_words(void* p, size_t words, hipStream_t s) {
+  if (words == 0) return hipSuccess;
+  int blocks = (int)((words + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  zero_words_kernel<<<blocks, 256, 0, s>>>((uint32_t*)p, words);
+  return hipGetLastError();
+}
+
 hipError_t launch_validate_values(const float* v, size_t n, unsigned long long* counters, hipStream_t s) {
   int blocks = (int)((n + 255) / 256);
   if (blocks > 4096) blocks = 4096;

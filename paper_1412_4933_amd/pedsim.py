@@ -80,6 +80,10 @@ def lib() -> ctypes.CDLL:
         L.sim_step_aco_tour.argtypes = [vp, i32, vp]
         L.sim_attach_tour.argtypes = [vp, vp, vp, vp]
         L.sim_set_neighbours.argtypes = [vp, i32]
+        L.sim_set_ranges.argtypes = [vp, i32, i32]
+        L.sim_set_range_tiling.argtypes = [vp, i32, i32, i32]
+        L.sim_get_range_tiling.argtypes = [vp, P(ctypes.c_int32)]
+        L.sim_range_weights.argtypes = [i32, i32, i32, P(ctypes.c_float), P(ctypes.c_float)]
         L.sim_stats.argtypes = [vp, P(SimStats), vp]
         L.sim_read_state.argtypes = [vp, vp, vp, vp, vp]
         L.sim_step_timed.argtypes = [vp, i32, i32, vp, P(ctypes.c_double), P(ctypes.c_int64), i32]
@@ -94,7 +98,8 @@ def lib() -> ctypes.CDLL:
         L.sim_destroy.restype = None
         for name in ("sim_scratch_bytes", "sim_create", "sim_step_lem", "sim_step_aco",
                      "sim_step_aco_tour", "sim_attach_tour", "sim_set_neighbours", "sim_stats",
-                     "sim_read_state"):
+                     "sim_read_state", "sim_set_ranges", "sim_set_range_tiling", "sim_get_range_tiling",
+                     "sim_range_weights"):
             getattr(L, name).restype = ctypes.c_int
         _bind_batch(L)
         _lib = L
@@ -178,6 +183,28 @@ def sim_attach_tour(h, tour, tour_shadow, stream=None) -> None:
 
 def sim_set_neighbours(h, n: int) -> None:
     _check(lib().sim_set_neighbours(h, int(n)), "sim_set_neighbours")
+
+
+def sim_set_ranges(h, scan: int, move: int) -> None:
+    _check(lib().sim_set_ranges(h, int(scan), int(move)), "sim_set_ranges")
+
+
+def sim_set_range_tiling(h, cols: int, rows: int, threads: int) -> None:
+    _check(lib().sim_set_range_tiling(h, int(cols), int(rows), int(threads)), "sim_set_range_tiling")
+
+
+def sim_get_range_tiling(h):
+    out = (ctypes.c_int32 * 3)()
+    _check(lib().sim_get_range_tiling(h, out), "sim_get_range_tiling")
+    return tuple(int(v) for v in out)
+
+
+def sim_range_weights(scan: int, move: int, beta: int):
+    """(diagonal[8], lateral[8]) heuristic weights of the range step (host only)."""
+    d = (ctypes.c_float * 8)()
+    la = (ctypes.c_float * 8)()
+    _check(lib().sim_range_weights(int(scan), int(move), int(beta), d, la), "sim_range_weights")
+    return np.array(d[:], np.float32), np.array(la[:], np.float32)
 
 
 def sim_step_aco_tour(h, nsteps: int, stream=None) -> None:
@@ -327,6 +354,19 @@ class Sim:
                             stream)
         if getattr(scenario, "neighbours", 5) != 5:
             sim_set_neighbours(self.h, scenario.neighbours)
+        self.ranges = getattr(scenario, "ranges", None)
+        self.range_tuned = None
+        if self.ranges is not None:
+            sim_set_ranges(self.h, *self.ranges)
+            if autotune:
+                from . import autotune as tuner
+                tl = tuner.cached_range(scenario, scenario.mode)
+                if tl is not None:
+                    try:
+                        sim_set_range_tiling(self.h, *tl)
+                        self.range_tuned = tuple(tl)
+                    except SimError:  # not allowed on this device: keep the default
+                        pass
         self.tuned = {}
         if autotune:
             from . import autotune as tuner
@@ -373,6 +413,19 @@ class Sim:
 
     def tiling(self, mode: int):
         return sim_get_tiling(self.h, mode)
+
+    def set_ranges(self, scan: int, move: int) -> None:
+        """Scanning and moving ranges of later LEM/ACO steps ((0, 0): the base
+        step); resets the range kernel's launch shape to the library default."""
+        sim_set_ranges(self.h, scan, move)
+        self.ranges = None if scan == 0 else (int(scan), int(move))
+        self.range_tuned = None
+
+    def set_range_tiling(self, cols: int, rows: int, threads: int) -> None:
+        sim_set_range_tiling(self.h, cols, rows, threads)
+
+    def range_tiling(self):
+        return sim_get_range_tiling(self.h)
 
     def state(self):
         """(code, ids, tau) copied to host numpy arrays."""

@@ -25,7 +25,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Optional
+from typing import Tuple, List, Optional
 
 import numpy as np
 
@@ -56,6 +56,7 @@ class Scenario:
     beta: int = 2
     tour: Optional[np.ndarray] = None  # float32 [N] initial tour lengths (tour variant), None = zeros
     neighbours: int = 5  # 5: F, FD+-, L+- (no backward cells); 8: all eight neighbours
+    ranges: Optional[Tuple[int, int]] = None  # (scanning range, moving range); None: the base step
 
     @property
     def cross_a(self) -> int:
@@ -145,7 +146,7 @@ def make_scenario(W: int, H: int, n_a: int, n_b: int, *, band_a: int,
                   mode: int = MODE_ACO, steps: int = 0, obstacle_frac: float = 0.0,
                   tau0: float = 1.0, rho: float = 0.1, dtau: float = 1.0,
                   alpha: int = 1, beta: int = 2, with_tau: Optional[bool] = None,
-                  neighbours: int = 5) -> Scenario:
+                  neighbours: int = 5, ranges: Optional[Tuple[int, int]] = None) -> Scenario:
     """Build one seeded scenario; `seed` drives placement and is also the
     step's RNG key."""
     if band_b is None:
@@ -160,7 +161,8 @@ def make_scenario(W: int, H: int, n_a: int, n_b: int, *, band_a: int,
     tau = np.full((2, H, W), np.float32(tau0), dtype=np.float32) if with_tau else None
     return Scenario(W=W, H=H, code=code, ids=ids, tau=tau, seed=seed, band_a=b_a,
                     band_b=b_b, n_a=n_a, n_b=n_b, mode=mode, steps=steps, tau0=tau0,
-                    rho=rho, dtau=dtau, alpha=alpha, beta=beta, neighbours=neighbours)
+                    rho=rho, dtau=dtau, alpha=alpha, beta=beta, neighbours=neighbours,
+                    ranges=ranges)
 
 
 def from_grid(code: np.ndarray, *, seed: int = 1, band_a: int = 1, band_b: int = 1,
@@ -205,6 +207,15 @@ def aco_nb8_1024x512(seed: int = 1) -> Scenario:
     candidate set (backward cells ranked last)."""
     return make_scenario(1024, 512, 50000, 50000, band_a=64, seed=seed, mode=MODE_ACO,
                          steps=2000, neighbours=8)
+
+
+def range_1024x512(mode: int = MODE_ACO, scan: int = 4, move: int = 2, seed: int = 1) -> Scenario:
+    """The 1024x512 workload (50,000 agents per group, same ACO parameters,
+    2,000 steps) with larger scanning and moving ranges (the paper's future
+    work, Sec. VII): by default agents scan 4 cells along each ray and move up
+    to 2 cells per step."""
+    return make_scenario(1024, 512, 50000, 50000, band_a=64, seed=seed, mode=mode,
+                         steps=2000, with_tau=True, ranges=(scan, move))
 
 
 def stress_4096x2048(mode: int = MODE_ACO, seed: int = 1) -> Scenario:

@@ -9,6 +9,7 @@ import os
 import subprocess
 import sys
 import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 import pytest
 
@@ -103,9 +104,9 @@ MUTANTS = {
 }
 
 
-@pytest.mark.slow
-@pytest.mark.parametrize("name", sorted(MUTANTS))
-def test_planted_mistake_fails_a_pin(name):
+def _run_mutant(name):
+    """Compile the mutant and run the pins against it; returns the pin run's
+    exit status (0 = the mutant passed every pin)."""
     old, new = MUTANTS[name][:2]
     nth = MUTANTS[name][2] if len(MUTANTS[name]) > 2 else None
     with open(SRC) as f:
@@ -118,6 +119,10 @@ def test_planted_mistake_fails_a_pin(name):
     at = -1
     for _ in range(nth + 1):
         at = src.index(old, at + 1)
+    pins = [os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+            os.path.join(ROOT, "tests", "test_oracle_range_pins.py")]
+    if name.startswith("range_"):  # the range pins first: they stop a range mutant sooner
+        pins.reverse()
     with tempfile.TemporaryDirectory() as d:
         msrc = os.path.join(d, "mutant.c")
         mlib = os.path.join(d, "libmutant.so")
@@ -125,9 +130,23 @@ def test_planted_mistake_fails_a_pin(name):
             f.write(src[:at] + new + src[at + len(old):])
         subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
                         "-o", mlib, msrc, "-lm"], check=True)
-        env = dict(os.environ, PEDSIM_ORACLE_LIB=mlib)
-        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                            os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                            os.path.join(ROOT, "tests", "test_oracle_range_pins.py")],
-                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
-        assert r.returncode != 0, f"mutant {name} passed every pin"
+        env = dict(os.environ, PEDSIM_ORACLE_LIB=mlib, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *pins],
+                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
+        return r.returncode
+
+
+@pytest.fixture(scope="module")
+def mutant_status():
+    """Every mutant's pin run, several at a time (each is one CPU-bound
+    process), so the suite's wall time stays a few minutes."""
+    workers = max(1, min(8, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                         else (os.cpu_count() or 1)))
+    with ThreadPoolExecutor(workers) as ex:
+        return dict(zip(sorted(MUTANTS), ex.map(_run_mutant, sorted(MUTANTS))))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_fails_a_pin(name, mutant_status):
+    assert mutant_status[name] != 0, f"mutant {name} passed every pin"
