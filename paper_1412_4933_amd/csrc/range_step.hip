@@ -147,6 +147,7 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
   unsigned long long* keys = (unsigned long long*)(smem + L.keys());
   uint8_t* req = smem + L.req();
   uint32_t* cnt = (uint32_t*)(smem + L.ctl());
+  float* eta_s = (float*)(cnt + 8);  // eta^beta: [0 lateral, 1 diagonal][free run - 1]
   float* tau_a = (float*)(smem + L.tau());  // ACO: [PH][PW] per plane
   float* tau_b = tau_a + (size_t)PW * PH;
 
@@ -217,6 +218,7 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
     }
     for (int i = threadIdx.x; i < KW * KH; i += nthreads) keys[i] = kNoClaim;
     if (threadIdx.x < 8) cnt[threadIdx.x] = 0u;
+    if (threadIdx.x < 2 * kRangeMax) eta_s[threadIdx.x] = P.eta[threadIdx.x / kRangeMax][threadIdx.x % kRangeMax];
   }
   __syncthreads();
 
@@ -277,7 +279,7 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
               eta[ray] = 0.0f;
               if (f[ray] >= 1) {
                 const int k = f[ray] < M ? f[ray] : M;
-                eta[ray] = P.eta[ray <= 2 ? 1 : 0][f[ray] - 1];
+                eta[ray] = eta_s[(ray <= 2 ? kRangeMax : 0) + f[ray] - 1];
                 tau[ray] = tp[(py + k * ray_dy(ray)) * PW + px + k * ray_dx(ray, d)];
               }
             }

@@ -49,7 +49,7 @@ struct RangeLayout {
   }
   __host__ __device__ size_t req() const { return keys() + (size_t)(TX + 2 * M) * (TY + 2 * M) * 8; }
   __host__ __device__ size_t ctl() const { return (req() + (size_t)TX * TY + 15) / 16 * 16; }
-  __host__ __device__ size_t tau() const { return ctl() + 8 * 4; }
+  __host__ __device__ size_t tau() const { return ctl() + 32 * 4; }  // ctl: 8 counters, 16 eta, pad
   __host__ __device__ size_t bytes() const {
     return tau() + (aco ? (size_t)2 * (TX + 6 * M) * (TY + 6 * M) * 4 : 0);
   }

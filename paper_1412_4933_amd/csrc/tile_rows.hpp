@@ -194,7 +194,6 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
   uint64_t* reqm = (uint64_t*)(smem + L.reqm());
   uint64_t* cwin = (uint64_t*)(smem + L.cwin());
   uint64_t* moved_m = (uint64_t*)(smem + L.moved());
-  uint64_t* unc_m = moved_m;  // during the steps: each row's uncontested targets of the current step
   uint32_t* ctl = (uint32_t*)(smem + L.ctl());
   uint32_t* ids = (uint32_t*)(smem + L.ids());
   uint32_t* tick = (uint32_t*)(smem + L.tick());
@@ -566,17 +565,8 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) Wt[q] &= ~twos;  // uncontested winners
-      // contested cells are queued; the uncontested ones move their ids row by
-      // row in the resolve phase (no queue)
-      const uint64_t live = live_window(3 * (steps - 1 - s) + 1, h, R, lane);
-      const uint64_t unc = ones & ~twos & live;
-      if (row_lane) unc_m[lane] = unc;
-      const int na = enqueue_row_bits(queue, twos & live, lane);
-      const bool any_unc = __ballot(unc != 0ull) != 0ull;
-      if (lane == 0) {
-        ctl[1] = (uint32_t)na;
-        ctl[2] = any_unc ? 1u : 0u;
-      }
+      const int na = enqueue_row_bits(queue, ones & live_window(3 * (steps - 1 - s) + 1, h, R, lane), lane);
+      if (lane == 0) ctl[1] = (uint32_t)na;
     }
     if (!NB8 && mask_wave) {
       uint64_t own[6];
@@ -602,96 +592,74 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) Wt[q] &= ~twos;  // uncontested winners
-      // contested cells are queued; the uncontested ones move their ids row by
-      // row in the resolve phase (no queue)
-      const uint64_t live = live_window(3 * (steps - 1 - s) + 1, h, R, lane);
-      const uint64_t unc = ones & ~twos & live;
-      if (row_lane) unc_m[lane] = unc;
-      const int na = enqueue_row_bits(queue, twos & live, lane);
-      const bool any_unc = __ballot(unc != 0ull) != 0ull;
-      if (lane == 0) {
-        ctl[1] = (uint32_t)na;
-        ctl[2] = any_unc ? 1u : 0u;
-      }
+      const int na = enqueue_row_bits(queue, ones & live_window(3 * (steps - 1 - s) + 1, h, R, lane), lane);
+      if (lane == 0) ctl[1] = (uint32_t)na;
     }
     __syncthreads();
 
     // ---- 4. resolve contests; every winner's id moves to its target --------
     const int na = (int)ctl[1];
-    const bool any_unc = ctl[2] != 0u;
-    // The winner from direction `best` moves into (r, c): its id (and, in the
-    // tour variant, its tour length grown by the move, and eq. 5's deposit on
-    // the entered cell). Targets were empty and sources occupied at the start
-    // of the step, so the moves never overlap.
-    auto move_in = [&](int r, int c, int best, uint32_t src_id) {
-      ids[r * 64 + c] = src_id;
-      if (MODE == 2) {
-        const int sr = r + dir_dr(best), sc = c + dir_dc(best);
-        const bool diagonal = best >= 2 && best <= 5;
-        const float len = tlen[sr * 64 + sc] + (diagonal ? S.step_diag : 1.0f);
-        tlen[r * 64 + c] = len;
-        const bool ga = NB8 ? (bool)((H(s, 0, sr) >> sc) & 1ull)
-                            : (best == 0 || best == 2 || best == 3 || (best >= 6 && ((H(s, 0, sr) >> sc) & 1ull)));
-        const int gp = ga ? 0 : 1;
-        float* tp = ga ? tau_a : tau_b;
-        int owed = s + 1;  // evaporations since the cell's last deposit, this step's included
-        for (int u = 0; u < s; ++u) {
-          const uint64_t entered = H(u + 1, gp, r) & ~(H(u, 0, r) | H(u, 1, r));
-          if ((entered >> c) & 1ull) owed = s - u;
-        }
-        float v = tp[r * 64 + c];
-        for (int u = 0; u <= s; ++u)
-          if (u > s - owed) v = S.keep * v;
-        tp[r * 64 + c] = v + S.dtau / len;
-      }
-    };
-    if (na > 0 || any_unc) {
-      // contested cells: the lowest (ticket, agent number) wins (Sec. IV.d)
+    if (na > 0) {
       for (int qi = tid; qi < na; qi += nthreads) {
         const uint32_t e = queue[qi];
         const int r = (int)(e & 63u), c = (int)((e >> 6) & 63u);
         uint32_t dirs = 0u;
 #pragma unroll
         for (int q = 0; q < 8; ++q) dirs |= (uint32_t)((reqm[q * R + r] >> c) & 1ull) << q;
-        // every direction's ticket and id in one round (clamped addresses;
-        // directions without a requester are ignored)
-        uint32_t tk[8], kk[8];
+        int best = __ffs(dirs) - 1;
+        uint32_t src_id;
+        if (dirs & (dirs - 1u)) {  // contested: lowest (ticket, agent number)
+          // every direction's ticket and id in one round (clamped addresses;
+          // directions without a requester are ignored)
+          uint32_t tk[8], kk[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          int sr = r + dir_dr(q), sc = c + dir_dc(q);
-          sr = sr < 0 ? 0 : (sr >= R ? R - 1 : sr);
-          sc = sc < 0 ? 0 : (sc > 63 ? 63 : sc);
-          kk[q] = ids[sr * 64 + sc];
-          if (kTicks) tk[q] = tick[sr * 64 + sc];
-        }
-        if (!kTicks) {  // the contenders' tickets, drawn again (independent chains)
-#pragma unroll
-          for (int q = 0; q < 8; ++q)
-            tk[q] = ((dirs >> q) & 1u) ? agent_words(kk[q] - 1u, t, S.key0, S.key1).w0 : 0xFFFFFFFFu;
-        }
-        uint32_t best_t = 0xFFFFFFFFu, src_id = 0xFFFFFFFFu;
-        int best = -1;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          if (((dirs >> q) & 1u) && (best < 0 || tk[q] < best_t || (tk[q] == best_t && kk[q] < src_id))) {
-            best = q;
-            best_t = tk[q];
-            src_id = kk[q];
+          for (int q = 0; q < 8; ++q) {
+            int sr = r + dir_dr(q), sc = c + dir_dc(q);
+            sr = sr < 0 ? 0 : (sr >= R ? R - 1 : sr);
+            sc = sc < 0 ? 0 : (sc > 63 ? 63 : sc);
+            kk[q] = ids[sr * 64 + sc];
+            if (kTicks) tk[q] = tick[sr * 64 + sc];
           }
-        }
-        atomicOr((unsigned long long*)&cwin[best * R + r], 1ull << c);
-        move_in(r, c, best, src_id);
-      }
-      // uncontested targets, row by row (lane = column)
-      if (any_unc) {
-        for (int r = wave; r < R; r += nwaves) {
-          const uint64_t u = unc_m[r];
-          if (u == 0ull || !((u >> lane) & 1ull)) continue;
-          int best = 0;
+          if (!kTicks) {  // the contenders' tickets, drawn again (independent chains)
 #pragma unroll
-          for (int q = 7; q >= 0; --q)
-            if ((reqm[q * R + r] >> lane) & 1ull) best = q;
-          move_in(r, lane, best, ids[(r + dir_dr(best)) * 64 + lane + dir_dc(best)]);
+            for (int q = 0; q < 8; ++q)
+              tk[q] = ((dirs >> q) & 1u) ? agent_words(kk[q] - 1u, t, S.key0, S.key1).w0 : 0xFFFFFFFFu;
+          }
+          uint32_t best_t = 0xFFFFFFFFu;
+          src_id = 0xFFFFFFFFu;
+          best = -1;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            if (((dirs >> q) & 1u) &&
+                (best < 0 || tk[q] < best_t || (tk[q] == best_t && kk[q] < src_id))) {
+              best = q;
+              best_t = tk[q];
+              src_id = kk[q];
+            }
+          }
+          atomicOr((unsigned long long*)&cwin[best * R + r], 1ull << c);
+        } else {
+          src_id = ids[(r + dir_dr(best)) * 64 + c + dir_dc(best)];
+        }
+        ids[r * 64 + c] = src_id;
+        if (MODE == 2) {  // the tour grows by the move's length; eq. 5's deposit on the entered cell
+          const int sr = r + dir_dr(best), sc = c + dir_dc(best);
+          const bool diagonal = best >= 2 && best <= 5;
+          const float len = tlen[sr * 64 + sc] + (diagonal ? S.step_diag : 1.0f);
+          tlen[r * 64 + c] = len;
+          const bool ga = NB8 ? (bool)((H(s, 0, sr) >> sc) & 1ull)
+                              : (best == 0 || best == 2 || best == 3 || (best >= 6 && ((H(s, 0, sr) >> sc) & 1ull)));
+          const int gp = ga ? 0 : 1;
+          float* tp = ga ? tau_a : tau_b;
+          int owed = s + 1;  // evaporations since the cell's last deposit, this step's included
+          for (int u = 0; u < s; ++u) {
+            const uint64_t entered = H(u + 1, gp, r) & ~(H(u, 0, r) | H(u, 1, r));
+            if ((entered >> c) & 1ull) owed = s - u;
+          }
+          float v = tp[r * 64 + c];
+          for (int u = 0; u <= s; ++u)
+            if (u > s - owed) v = S.keep * v;
+          tp[r * 64 + c] = v + S.dtau / len;
         }
       }
       __syncthreads();
