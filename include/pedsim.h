@@ -260,6 +260,28 @@ const char* sim_kernel_name(int32_t kind);
 void sim_destroy(sim_handle* h);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): create +
+ * nsteps steps of `mode` (SIM_MODE_LEM or SIM_MODE_ACO) + stats in one call,
+ * with results identical to sim_create / sim_step_lem or sim_step_aco /
+ * sim_stats on the same planes. The caller passes the state planes (layout,
+ * validation and errors as sim_create; they hold the state after the last
+ * step when the call returns) and a host sim_stats_t; no scratch argument:
+ * the shadow planes and counters live in a static device array of the
+ * library, SIM_NOALLOC_SCRATCH_BYTES per GPU (allocated when the library is
+ * loaded and held until the process ends), so the call makes no hipMalloc,
+ * hipFree or other allocation, host or device. SIM_ESCRATCH when the
+ * scenario's scratch (sim_scratch_bytes) exceeds that size: about 2.5M cells.
+ * Every call on a GPU shares that GPU's array: calls within one process are
+ * serialised per device by a lock, and the array keeps the last call's
+ * contents (each call clears what it needs at zero itself). Synchronises
+ * `stream`.
+ */
+#define SIM_NOALLOC_SCRATCH_BYTES (32u << 20)
+int sim_run_noalloc(const sim_params* p, int32_t mode, uint8_t* d_code, uint32_t* d_id, float* d_tau,
+                    int32_t nsteps, void* stream, sim_stats_t* out);
+
+/*
  * Batched form: many independent scenarios (any sizes; LEM, ACO or the tour
  * variant each)
  * advanced together by one persistent kernel per launch, whose work items are

@@ -10,6 +10,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "pedsim.h"
@@ -409,6 +410,25 @@ int init_handle(sim_handle* h, const sim_params* p, uint8_t* d_code, uint32_t* d
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch for callers that cannot allocate (sim_run_noalloc): one static
+// device array per GPU, held until the process ends. Host code must never
+// pass `scratch` itself to a kernel or a copy (in host code the name is a
+// host-side stand-in, not a device address): it uses the address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device and kept in g_noalloc_ptr.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = (size_t)SIM_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_noalloc_mu[kNoAllocMaxDevices];  // one call at a time per device
+uint8_t* g_noalloc_ptr[kNoAllocMaxDevices];   // device address of `scratch` per device
+
+}  // namespace
+
 extern "C" {
 
 const char* sim_strerror(int code) {
@@ -627,6 +647,33 @@ const char* sim_kernel_name(int32_t kind) {
     case 1: return "copy_back";
     default: return "";
   }
+}
+
+int sim_run_noalloc(const sim_params* p, int32_t mode, uint8_t* d_code, uint32_t* d_id, float* d_tau,
+                    int32_t nsteps, void* stream, sim_stats_t* out) {
+  int e = check_params(p);
+  if (e) return e;
+  if (!d_code || !d_id || !out || nsteps < 0 || (mode != kModeLem && mode != kModeAco)) return SIM_EINVAL;
+  if (mode == kModeAco && !d_tau) return SIM_ENOTAU;
+  const ScratchLayout L = layout_of(p);
+  if (L.total > kNoAllocScratchBytes) return SIM_ESCRATCH;
+  int dev = 0;
+  PEDSIM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return SIM_EINVAL;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu[dev]);
+  if (!g_noalloc_ptr[dev]) {  // first call on this device (it is current)
+    void* ptr = nullptr;
+    PEDSIM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return SIM_EHIP;
+    g_noalloc_ptr[dev] = (uint8_t*)ptr;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  sim_handle h;  // on the stack: this call allocates nothing, host or device
+  e = init_handle(&h, p, d_code, d_id, d_tau, g_noalloc_ptr[dev], L, s);
+  if (e) return e;
+  e = run_steps(&h, mode, nsteps, s, nullptr, nullptr, nullptr);
+  if (e) return e;
+  return sim_stats(&h, out, stream);  // synchronises: the array is free for the next call
 }
 
 void sim_destroy(sim_handle* h) { delete h; }

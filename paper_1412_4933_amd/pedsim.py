@@ -85,6 +85,7 @@ def lib() -> ctypes.CDLL:
         L.sim_get_range_tiling.argtypes = [vp, P(ctypes.c_int32)]
         L.sim_range_weights.argtypes = [i32, i32, i32, P(ctypes.c_float), P(ctypes.c_float)]
         L.sim_stats.argtypes = [vp, P(SimStats), vp]
+        L.sim_run_noalloc.argtypes = [P(SimParams), i32, vp, vp, vp, i32, vp, P(SimStats)]
         L.sim_read_state.argtypes = [vp, vp, vp, vp, vp]
         L.sim_step_timed.argtypes = [vp, i32, i32, vp, P(ctypes.c_double), P(ctypes.c_int64), i32]
         L.sim_step_timed.restype = ctypes.c_int
@@ -99,7 +100,7 @@ def lib() -> ctypes.CDLL:
         for name in ("sim_scratch_bytes", "sim_create", "sim_step_lem", "sim_step_aco",
                      "sim_step_aco_tour", "sim_attach_tour", "sim_set_neighbours", "sim_stats",
                      "sim_read_state", "sim_set_ranges", "sim_set_range_tiling", "sim_get_range_tiling",
-                     "sim_range_weights"):
+                     "sim_range_weights", "sim_run_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         _bind_batch(L)
         _lib = L
@@ -205,6 +206,15 @@ def sim_range_weights(scan: int, move: int, beta: int):
     la = (ctypes.c_float * 8)()
     _check(lib().sim_range_weights(int(scan), int(move), int(beta), d, la), "sim_range_weights")
     return np.array(d[:], np.float32), np.array(la[:], np.float32)
+
+
+def sim_run_noalloc(params: SimParams, mode: int, code, ids, tau, nsteps: int, stream=None) -> dict:
+    """Create, step and count in one call with the library's static scratch
+    (no allocation); the planes hold the new state afterwards."""
+    s = SimStats()
+    _check(lib().sim_run_noalloc(ctypes.byref(params), int(mode), _ptr(code), _ptr(ids), _ptr(tau),
+                                 int(nsteps), _stream(stream), ctypes.byref(s)), "sim_run_noalloc")
+    return s.as_dict()
 
 
 def sim_step_aco_tour(h, nsteps: int, stream=None) -> None:
