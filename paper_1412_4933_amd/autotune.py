@@ -54,7 +54,8 @@ BATCH_CANDIDATES = [
 RANGE_CANDIDATES = [
     (64, 16, 256), (64, 24, 256), (64, 32, 256), (64, 48, 256), (64, 64, 256), (64, 32, 512),
     (64, 64, 512), (128, 16, 256), (128, 32, 256), (128, 32, 512), (32, 32, 256), (32, 16, 128),
-    (48, 32, 256), (96, 32, 256),
+    (48, 32, 256), (96, 32, 256), (64, 16, 512), (128, 16, 512), (64, 24, 512), (32, 32, 512),
+    (96, 16, 512), (48, 48, 512),
 ]
 
 _cache: Dict[str, tuple] = {}

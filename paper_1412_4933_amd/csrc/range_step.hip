@@ -129,13 +129,18 @@ __device__ __forceinline__ uint32_t div_magic(uint32_t d) {
 }
 __device__ __forceinline__ int fast_div(int i, uint32_t m) { return (int)__umulhi((uint32_t)i, m); }
 
-template <int MODE>
+// Number of lanes below this one whose bit is set in `bal`.
+__device__ __forceinline__ int lanes_below_range(uint64_t bal) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+}
+
+template <int MODE, int S>
 __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P, int last) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int ntiles = P.tiles_x * P.tiles_y;
   const int tile = range_tile_of_block(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
-  const int TX = P.TX, TY = P.TY, S = P.S, M = P.M;
+  const int TX = P.TX, TY = P.TY, M = P.M;
   const int hc = 2 * M + S;  // code halo
   const int CW = TX + 2 * hc, CH = TY + 2 * hc;
   const int RW = TX + 4 * M, RH = TY + 4 * M;  // request region: agents up to 2M from the interior
@@ -144,61 +149,52 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
   const RangeLayout L{TX, TY, S, M, MODE != kModeLem};
   uint8_t* code = smem + L.code();
   uint32_t* ids = (uint32_t*)(smem + L.ids());
+  uint8_t* rq = smem + L.req();                    // request byte per request-region cell
+  uint16_t* list = (uint16_t*)(smem + L.list());   // the request region's agents, compacted
   unsigned long long* keys = (unsigned long long*)(smem + L.keys());
-  uint8_t* req = smem + L.req();
-  uint32_t* cnt = (uint32_t*)(smem + L.ctl());
-  float* eta_s = (float*)(cnt + 8);  // eta^beta: [0 lateral, 1 diagonal][free run - 1]
-  float* tau_a = (float*)(smem + L.tau());  // ACO: [PH][PW] per plane
+  uint32_t* claims = (uint32_t*)(smem + L.claims());  // claims per key-region cell
+  uint32_t* cnt = (uint32_t*)(smem + L.ctl());     // [0..4] counters, [5] agents in the list
+  float* eta_s = (float*)(cnt + 8);                // eta^beta: [0 lateral, 1 diagonal][free run - 1]
+  float* tau_a = (float*)(smem + L.tau());         // ACO: [PH][PW] per plane
   float* tau_b = tau_a + (size_t)PW * PH;
 
   const int x0 = (tile % P.tiles_x) * TX, y0 = (tile / P.tiles_x) * TY;
   const int W = P.W, H = P.H;
   const int lane = threadIdx.x & 63;
   const int nthreads = blockDim.x;
+  const uint32_t mc = div_magic((uint32_t)CW), mr = div_magic((uint32_t)RW), mp = div_magic((uint32_t)PW);
 
   // 1. stage the codes of the region (interior + 2M + S; outside the grid
   //    reads as wall), the ids of the request region and, for ACO, both
   //    pheromone planes of the interior + 3M (every landing cell of a
-  //    requester and every interior cell); clear the keys. Each thread keeps
-  //    kStageBatch loads in flight before it writes them to LDS.
+  //    requester and every interior cell); clear the keys and claim counts.
+  //    Every load of a round is issued before the round's LDS stores.
   {
-    const uint32_t mc = div_magic((uint32_t)CW);
-    for (int i0 = threadIdx.x; i0 < CW * CH; i0 += nthreads * kStageBatch) {
-      uint32_t v[kStageBatch];
+    const size_t plane = (size_t)W * H;
+    const int per = nthreads * kStageBatch;
+    const int rounds_c = (CW * CH + per - 1) / per, rounds_i = (RW * RH + per - 1) / per;
+    const int rounds_p = MODE != kModeLem ? (PW * PH + per - 1) / per : 0;
+    const int rounds = rounds_c > rounds_i ? (rounds_c > rounds_p ? rounds_c : rounds_p)
+                                           : (rounds_i > rounds_p ? rounds_i : rounds_p);
+    for (int rd = 0; rd < rounds; ++rd) {
+      const int i0 = rd * per + threadIdx.x;
+      uint32_t vc[kStageBatch], vi[kStageBatch];
+      float va[kStageBatch], vb[kStageBatch];
 #pragma unroll
       for (int u = 0; u < kStageBatch; ++u) {
         const int i = i0 + u * nthreads;
-        const int r = fast_div(i, mc), c = i - r * CW;
-        const int gx = x0 - hc + c, gy = y0 - hc + r;
-        v[u] = (i < CW * CH && gx >= 0 && gx < W && gy >= 0 && gy < H) ? P.code_in[(size_t)gy * W + gx]
-                                                                          : (uint32_t)kWall;
-      }
-#pragma unroll
-      for (int u = 0; u < kStageBatch; ++u)
-        if (i0 + u * nthreads < CW * CH) code[i0 + u * nthreads] = (uint8_t)v[u];
-    }
-    const uint32_t mr = div_magic((uint32_t)RW);
-    for (int i0 = threadIdx.x; i0 < RW * RH; i0 += nthreads * kStageBatch) {
-      uint32_t v[kStageBatch];
-#pragma unroll
-      for (int u = 0; u < kStageBatch; ++u) {
-        const int i = i0 + u * nthreads;
-        const int r = fast_div(i, mr), c = i - r * RW;
-        const int gx = x0 - 2 * M + c, gy = y0 - 2 * M + r;
-        v[u] = (i < RW * RH && gx >= 0 && gx < W && gy >= 0 && gy < H) ? P.id_in[(size_t)gy * W + gx] : 0u;
-      }
-#pragma unroll
-      for (int u = 0; u < kStageBatch; ++u)
-        if (i0 + u * nthreads < RW * RH) ids[i0 + u * nthreads] = v[u];
-    }
-    if (MODE != kModeLem) {
-      const size_t plane = (size_t)W * H;
-      const uint32_t mp = div_magic((uint32_t)PW);
-      for (int i0 = threadIdx.x; i0 < PW * PH; i0 += nthreads * kStageBatch) {
-        float va[kStageBatch], vb[kStageBatch];
-#pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) {
-          const int i = i0 + u * nthreads;
+        {
+          const int r = fast_div(i, mc), c = i - r * CW;
+          const int gx = x0 - hc + c, gy = y0 - hc + r;
+          vc[u] = (i < CW * CH && gx >= 0 && gx < W && gy >= 0 && gy < H) ? P.code_in[(size_t)gy * W + gx]
+                                                                            : (uint32_t)kWall;
+        }
+        {
+          const int r = fast_div(i, mr), c = i - r * RW;
+          const int gx = x0 - 2 * M + c, gy = y0 - 2 * M + r;
+          vi[u] = (i < RW * RH && gx >= 0 && gx < W && gy >= 0 && gy < H) ? P.id_in[(size_t)gy * W + gx] : 0u;
+        }
+        if (MODE != kModeLem) {
           const int r = fast_div(i, mp), c = i - r * PW;
           const int gx = x0 - 3 * M + c, gy = y0 - 3 * M + r;
           const bool in = i < PW * PH && gx >= 0 && gx < W && gy >= 0 && gy < H;
@@ -206,102 +202,155 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
           va[u] = in ? P.tau_in[gi] : 0.0f;
           vb[u] = in ? P.tau_in[plane + gi] : 0.0f;
         }
+      }
 #pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) {
-          const int i = i0 + u * nthreads;
-          if (i < PW * PH) {
-            tau_a[i] = va[u];
-            tau_b[i] = vb[u];
-          }
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int i = i0 + u * nthreads;
+        if (i < CW * CH) code[i] = (uint8_t)vc[u];
+        if (i < RW * RH) ids[i] = vi[u];
+        if (MODE != kModeLem && i < PW * PH) {
+          tau_a[i] = va[u];
+          tau_b[i] = vb[u];
         }
       }
     }
-    for (int i = threadIdx.x; i < KW * KH; i += nthreads) keys[i] = kNoClaim;
+    for (int i = threadIdx.x; i < KW * KH; i += nthreads) {
+      keys[i] = kNoClaim;
+      claims[i] = 0u;
+    }
     if (threadIdx.x < 8) cnt[threadIdx.x] = 0u;
     if (threadIdx.x < 2 * kRangeMax) eta_s[threadIdx.x] = P.eta[threadIdx.x / kRangeMax][threadIdx.x % kRangeMax];
   }
   __syncthreads();
 
-  // 2. requests of every agent of the request region
-  {
-    const uint32_t mr = div_magic((uint32_t)RW);
-    for (int i = threadIdx.x; i < RW * RH; i += nthreads) {
+  // 2. list the agents of the request region (one LDS atomic per wave); clear
+  //    every cell's request
+  for (int i0 = threadIdx.x - lane; i0 < RW * RH; i0 += nthreads) {
+    const int i = i0 + lane;
+    bool agent = false;
+    if (i < RW * RH) {
       const int r = fast_div(i, mr), c = i - r * RW;
-      const int cx = c + S, cy = r + S;  // code-region coordinates
-      const int g = code[cy * CW + cx];
-      const int ix = c - 2 * M, iy = r - 2 * M;  // interior coordinates
-      const bool interior = ix >= 0 && ix < TX && iy >= 0 && iy < TY;
-      int choice = -1, len = 0;
-      if (g == kGroupA || g == kGroupB) {
-        const int d = g == kGroupA ? 1 : -1;
-        int f[5], d2[5];
-        bool side = false;
+      const int g = code[(r + S) * CW + c + S];
+      agent = g == kGroupA || g == kGroupB;
+      rq[i] = 0u;
+    }
+    const uint64_t bal = __ballot(agent);
+    if (bal) {
+      uint32_t base = 0u;
+      if (lane == 0) base = atomicAdd(&cnt[5], (uint32_t)__popcll(bal));
+      base = __shfl(base, 0);
+      if (agent) list[base + lanes_below_range(bal)] = (uint16_t)i;
+    }
+  }
+  __syncthreads();
+  const int n_agents = (int)cnt[5];
+
+  // 3. requests: every listed agent scans its rays in LDS and chooses (the
+  //    forward ray without a draw; a side ray by eq. 1 or eq. 2 with the
+  //    agent's Philox words 1 and 2); every landing cell counts its claims
+  for (int t = threadIdx.x; t < n_agents; t += nthreads) {
+    const int i = list[t];
+    const int r = fast_div(i, mr), c = i - r * RW;
+    const int cx = c + S, cy = r + S;  // code-region coordinates
+    const int g = code[cy * CW + cx];
+    const int d = g == kGroupA ? 1 : -1;
+    const int at = cy * CW + cx;
+    // the cell next to the agent on each ray first: an agent with all five
+    // blocked (most of a jam) makes no request
+    uint32_t first[5];
 #pragma unroll
-        for (int ray = 0; ray < 5; ++ray) {
-          const int ux = ray_dx(ray, d), uy = ray_dy(ray);
-          // all S cells of the ray read at once (independent LDS loads), the
-          // free run counted afterwards
-          const int step = uy * CW + ux;
-          const int at = cy * CW + cx;
-          uint32_t v[kRangeMax];
+    for (int ray = 0; ray < 5; ++ray) first[ray] = code[at + ray_dy(ray) * CW + ray_dx(ray, d)];
+    if (first[0] != kEmpty && first[1] != kEmpty && first[2] != kEmpty && first[3] != kEmpty &&
+        first[4] != kEmpty)
+      continue;
+    int f[5], d2[5];
+    bool side = false;
 #pragma unroll
-          for (int j = 0; j < kRangeMax; ++j) v[j] = j < S ? code[at + (j + 1) * step] : (uint32_t)kWall;
-          int j = 0;
-          bool open = true;
+    for (int ray = 0; ray < 5; ++ray) {
+      const int ux = ray_dx(ray, d), uy = ray_dy(ray);
+      // the rest of the ray read at once (independent LDS loads), the free
+      // run counted afterwards
+      const int step = uy * CW + ux;
+      uint32_t v[S];
+      v[0] = first[ray];
 #pragma unroll
-          for (int q = 0; q < kRangeMax; ++q) {
-            open = open && v[q] == kEmpty;
-            j += open ? 1 : 0;
-          }
-          f[ray] = j;
-          const int k = j < M ? j : M;
-          const int a = ray <= 2 ? 1 : 0;
-          const int b = ray == 0 ? 0 : 1;
-          const int dx = M + 1 - a * k;
-          d2[ray] = dx * dx + b * k * k;
-          side |= ray > 0 && j >= 1;
-        }
-        if (f[0] >= 1 || side) {
-          const uint32_t k_agent = ids[i] - 1u;
-          const Words w = agent_words(k_agent, P.t, P.key0, P.key1);
-          if (f[0] >= 1) {
-            choice = 0;
-          } else if (MODE == kModeLem) {
-            choice = range_lem(f, d2, w.w1, w.w2);
-          } else {
-            // the agent in pheromone-region coordinates
-            const int px = c + M, py = r + M;
-            const float* tp = g == kGroupA ? tau_a : tau_b;
-            float tau[5], eta[5];
+      for (int j = 1; j < S; ++j) v[j] = code[at + (j + 1) * step];
+      int j = 0;
+      bool open = true;
 #pragma unroll
-            for (int ray = 1; ray <= 4; ++ray) {
-              tau[ray] = 0.0f;
-              eta[ray] = 0.0f;
-              if (f[ray] >= 1) {
-                const int k = f[ray] < M ? f[ray] : M;
-                eta[ray] = eta_s[(ray <= 2 ? kRangeMax : 0) + f[ray] - 1];
-                tau[ray] = tp[(py + k * ray_dy(ray)) * PW + px + k * ray_dx(ray, d)];
-              }
-            }
-            choice = range_aco(f, d2, tau, eta, P.alpha, w.w1, w.w2);
-          }
-          len = f[choice] < M ? f[choice] : M;
-          // landing cell in key-region coordinates; farther ones are not needed
-          const int kx = c - M + len * ray_dx(choice, d);
-          const int ky = r - M + len * ray_dy(choice);
-          if (kx >= 0 && kx < KW && ky >= 0 && ky < KH) {
-            const unsigned long long key = ((unsigned long long)w.w0 << 32) |
-                                           ((unsigned long long)k_agent << 1) | (unsigned long long)(g - 1);
-            atomicMin(&keys[ky * KW + kx], key);
-          }
-        }
+      for (int q = 0; q < S; ++q) {
+        open = open && v[q] == kEmpty;
+        j += open ? 1 : 0;
       }
-      if (interior) req[iy * TX + ix] = choice >= 0 ? (uint8_t)((choice + 1) | (len << 3)) : (uint8_t)0;
+      f[ray] = j;
+      const int k = j < M ? j : M;
+      const int a = ray <= 2 ? 1 : 0;
+      const int b = ray == 0 ? 0 : 1;
+      const int dx = M + 1 - a * k;
+      d2[ray] = dx * dx + b * k * k;
+      side |= ray > 0 && j >= 1;
+    }
+    int choice = -1;
+    if (f[0] >= 1) {
+      choice = 0;
+    } else if (side) {
+      const Words w = agent_words(ids[i] - 1u, P.t, P.key0, P.key1);
+      if (MODE == kModeLem) {
+        choice = range_lem(f, d2, w.w1, w.w2);
+      } else {
+        const int px = c + M, py = r + M;  // the agent in pheromone-region coordinates
+        const float* tp = g == kGroupA ? tau_a : tau_b;
+        float tau[5], eta[5];
+#pragma unroll
+        for (int ray = 1; ray <= 4; ++ray) {
+          tau[ray] = 0.0f;
+          eta[ray] = 0.0f;
+          if (f[ray] >= 1) {
+            const int k = f[ray] < M ? f[ray] : M;
+            eta[ray] = eta_s[(ray <= 2 ? kRangeMax : 0) + f[ray] - 1];
+            tau[ray] = tp[(py + k * ray_dy(ray)) * PW + px + k * ray_dx(ray, d)];
+          }
+        }
+        choice = range_aco(f, d2, tau, eta, P.alpha, w.w1, w.w2);
+      }
+    }
+    if (choice >= 0) {
+      const int len = f[choice] < M ? f[choice] : M;
+      rq[i] = (uint8_t)((choice + 1) | (len << 3));
+      // landing cell in key-region coordinates; farther ones are not needed
+      const int kx = c - M + len * ray_dx(choice, d), ky = r - M + len * ray_dy(choice);
+      if (kx >= 0 && kx < KW && ky >= 0 && ky < KH) atomicAdd(&claims[ky * KW + kx], 1u);
     }
   }
   __syncthreads();
 
-  // 3. commit, pheromone (eq. 3 then eq. 4) and counters over the interior
+  // 4. resolve: a landing cell with one claim goes to its claimant; one with
+  //    several to the lowest (Philox word 0, agent number), by a 64-bit LDS
+  //    atomic min of (word 0 << 32 | agent number << 1 | group - 1), whatever
+  //    the order of the claims
+  for (int t = threadIdx.x; t < n_agents; t += nthreads) {
+    const int i = list[t];
+    const int q = rq[i];
+    if (!q) continue;
+    const int r = fast_div(i, mr), c = i - r * RW;
+    const int g = code[(r + S) * CW + c + S];
+    const int ray = (q & 7) - 1, len = q >> 3;
+    const int d = g == kGroupA ? 1 : -1;
+    const int kx = c - M + len * ray_dx(ray, d), ky = r - M + len * ray_dy(ray);
+    if (kx < 0 || kx >= KW || ky < 0 || ky >= KH) continue;
+    const int ki = ky * KW + kx;
+    const uint32_t k_agent = ids[i] - 1u;
+    const unsigned long long who = ((unsigned long long)k_agent << 1) | (unsigned long long)(g - 1);
+    if (claims[ki] == 1u) {
+      keys[ki] = who;
+    } else {
+      const uint32_t w0 = agent_words(k_agent, P.t, P.key0, P.key1).w0;
+      atomicMin(&keys[ki], ((unsigned long long)w0 << 32) | who);
+    }
+  }
+  __syncthreads();
+
+  // 5. commit, pheromone (eq. 3 then eq. 4) and counters over the interior
   uint32_t n_a = 0, n_b = 0, c_a = 0, c_b = 0, moved = 0;
   const size_t plane = (size_t)W * H;
   {
@@ -322,10 +371,11 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
           moved += 1;
         }
       } else if (g0 == kGroupA || g0 == kGroupB) {
-        nid = ids[(iy + 2 * M) * RW + ix + 2 * M];
-        const int rq = req[i];
-        if (rq) {
-          const int ray = (rq & 7) - 1, len = rq >> 3;
+        const int ri = (iy + 2 * M) * RW + ix + 2 * M;
+        nid = ids[ri];
+        const int q = rq[ri];
+        if (q) {
+          const int ray = (q & 7) - 1, len = q >> 3;
           const int d = g0 == kGroupA ? 1 : -1;
           const int kx = ix + M + len * ray_dx(ray, d), ky = iy + M + len * ray_dy(ray);
           const unsigned long long key = keys[ky * KW + kx];
@@ -374,20 +424,34 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
   }
 }
 
-template <int MODE>
+template <int MODE, int S>
 hipError_t launch_range_mode(const RangeScenario& P, int threads, int last, hipStream_t s) {
   const size_t lds = RangeLayout{P.TX, P.TY, P.S, P.M, MODE != kModeLem}.bytes();
   static bool attr_done = false;
   if (!attr_done) {
-    (void)hipFuncSetAttribute((const void*)range_kernel<MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)range_kernel<MODE, S>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               max_dynamic_lds());
     (void)hipGetLastError();  // an unsupported attribute value must not linger as the last error
     attr_done = true;
   }
   const int ntiles = P.tiles_x * P.tiles_y;
   const int blocks = ((ntiles + 7) / 8) * 8;
-  range_kernel<MODE><<<blocks, threads, lds, s>>>(P, last);
+  range_kernel<MODE, S><<<blocks, threads, lds, s>>>(P, last);
   return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_range_scan(const RangeScenario& P, int threads, int last, hipStream_t s) {
+  switch (P.S) {
+    case 1: return launch_range_mode<MODE, 1>(P, threads, last, s);
+    case 2: return launch_range_mode<MODE, 2>(P, threads, last, s);
+    case 3: return launch_range_mode<MODE, 3>(P, threads, last, s);
+    case 4: return launch_range_mode<MODE, 4>(P, threads, last, s);
+    case 5: return launch_range_mode<MODE, 5>(P, threads, last, s);
+    case 6: return launch_range_mode<MODE, 6>(P, threads, last, s);
+    case 7: return launch_range_mode<MODE, 7>(P, threads, last, s);
+    default: return launch_range_mode<MODE, 8>(P, threads, last, s);
+  }
 }
 
 }  // namespace
@@ -395,8 +459,8 @@ hipError_t launch_range_mode(const RangeScenario& P, int threads, int last, hipS
 hipError_t launch_range(const RangeScenario& P, int mode, int threads, int last, hipStream_t s) {
   if (threads < 64 || threads > kRangeMaxThreads || threads % 64) return hipErrorInvalidValue;
   if (P.S < 1 || P.S > kRangeMax || P.M < 1 || P.M > P.S) return hipErrorInvalidValue;
-  return mode == kModeLem ? launch_range_mode<kModeLem>(P, threads, last, s)
-                          : launch_range_mode<kModeAco>(P, threads, last, s);
+  return mode == kModeLem ? launch_range_scan<kModeLem>(P, threads, last, s)
+                          : launch_range_scan<kModeAco>(P, threads, last, s);
 }
 
 }  // namespace pedsim

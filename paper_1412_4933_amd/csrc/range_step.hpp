@@ -32,23 +32,26 @@ struct RangeScenario {
   float eta[2][kRangeMax];  // eta^beta of a side ray: [0 lateral, 1 diagonal][free run - 1]
 };
 
-// LDS of one workgroup: codes of the interior plus a 2M + S halo, ids of the
-// interior plus a 2M halo, claim keys of the interior plus an M halo, the
-// interior's requests, counters, and for ACO both pheromone planes of the
+// LDS of one workgroup: codes of the interior plus a 2M + S halo; ids, request
+// bytes and the compacted agent list of the request region (the interior plus
+// a 2M halo); claim keys and claim counts of the interior plus an M halo;
+// counters and the heuristic table; for ACO, both pheromone planes of the
 // interior plus a 3M halo.
 struct RangeLayout {
   int TX, TY, S, M;
   bool aco;
+  __host__ __device__ static size_t up16(size_t v) { return (v + 15) / 16 * 16; }
+  __host__ __device__ size_t rcells() const { return (size_t)(TX + 4 * M) * (TY + 4 * M); }
+  __host__ __device__ size_t kcells() const { return (size_t)(TX + 2 * M) * (TY + 2 * M); }
   __host__ __device__ size_t code() const { return 0; }
-  __host__ __device__ size_t code_bytes() const {
-    return (size_t)(TX + 2 * (2 * M + S)) * (size_t)(TY + 2 * (2 * M + S));
+  __host__ __device__ size_t ids() const {
+    return up16((size_t)(TX + 2 * (2 * M + S)) * (size_t)(TY + 2 * (2 * M + S)));
   }
-  __host__ __device__ size_t ids() const { return (code_bytes() + 15) / 16 * 16; }
-  __host__ __device__ size_t keys() const {
-    return (ids() + (size_t)(TX + 4 * M) * (TY + 4 * M) * 4 + 15) / 16 * 16;
-  }
-  __host__ __device__ size_t req() const { return keys() + (size_t)(TX + 2 * M) * (TY + 2 * M) * 8; }
-  __host__ __device__ size_t ctl() const { return (req() + (size_t)TX * TY + 15) / 16 * 16; }
+  __host__ __device__ size_t req() const { return ids() + rcells() * 4; }
+  __host__ __device__ size_t list() const { return up16(req() + rcells()); }
+  __host__ __device__ size_t keys() const { return up16(list() + rcells() * 2); }
+  __host__ __device__ size_t claims() const { return keys() + kcells() * 8; }
+  __host__ __device__ size_t ctl() const { return up16(claims() + kcells() * 4); }
   __host__ __device__ size_t tau() const { return ctl() + 32 * 4; }  // ctl: 8 counters, 16 eta, pad
   __host__ __device__ size_t bytes() const {
     return tau() + (aco ? (size_t)2 * (TX + 6 * M) * (TY + 6 * M) * 4 : 0);

@@ -96,7 +96,7 @@ def test_range_one_one_is_the_base_step(pedsim, mode):
 # most LDS per cell, so they get the smaller shapes
 TILINGS = [((3, 2), t) for t in [(16, 8, 64), (32, 8, 128), (64, 16, 256), (64, 32, 512), (128, 24, 256),
                                    (48, 40, 192), (256, 8, 512), (64, 64, 256)]] + \
-          [((8, 8), t) for t in [(16, 8, 64), (32, 8, 128), (64, 16, 256), (64, 32, 512), (128, 8, 256),
+          [((8, 8), t) for t in [(16, 8, 64), (32, 8, 128), (64, 16, 256), (32, 16, 512), (96, 8, 256),
                                    (48, 40, 192), (24, 24, 320)]]
 
 
