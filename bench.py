@@ -400,8 +400,8 @@ def main():
     def make_sim():
         sim = pedsim.Sim(scn, stream=stream)
         if tiling_arg is not None:
-            if getattr(scn, "ranges", None) is not None:  # cols,rows,1,threads for the range kernel
-                sim.set_range_tiling(tiling_arg[0], tiling_arg[1], tiling_arg[3])
+            if getattr(scn, "ranges", None) is not None:  # cols,rows,steps,threads for the range kernel
+                sim.set_range_tiling(*tiling_arg)
             else:
                 sim.set_tiling(mode, *tiling_arg)
         return sim
@@ -449,8 +449,7 @@ def main():
     prof = make_sim()
     ranged = getattr(scn, "ranges", None) is not None
     if ranged:  # range kernel: one step per launch, tiles of cols x rows cells
-        cols, rows, threads = pedsim.sim_get_range_tiling(prof.h)
-        tiling = (cols, rows, 1, threads)
+        tiling = pedsim.sim_get_range_tiling(prof.h)  # (cols, rows, steps per launch, threads)
         tiling_source = ("--tiling" if tiling_arg is not None else "library default") + \
             " (range kernel: cols, rows, steps per launch, threads)"
     else:

@@ -188,23 +188,27 @@ int sim_set_neighbours(sim_handle* h, int32_t n);
  *     (Philox word 0, agent number) among the agents landing on it; then
  *     eq. 3 and eq. 4 on every cell, as in the base step.
  * With scan = move = 1 every rule is the base step's, and the results are
- * identical to it. scan = move = 0 returns h to the base step. One launch
- * per step (its dependence reaches 2*move + scan cells, so several steps
- * per launch would need a wide halo). SIM_EINVAL for other values, on a
+ * identical to it. scan = move = 0 returns h to the base step. A step's
+ * dependence reaches 2*move + scan cells, so a launch of k steps stages a halo
+ * of k times that (sim_set_range_tiling). SIM_EINVAL for other values, on a
  * handle with the eight-neighbour set, and for sim_step_aco_tour while
  * ranges are set (not combined).
  */
 int sim_set_ranges(sim_handle* h, int32_t scan, int32_t move);
 
 /* Launch shape of the range step (results never depend on it): tile
- * interiors of cols (16..256) x rows (8..256) cells, `threads` per workgroup
- * (multiple of 64, <= 512); the workgroup keeps the codes of the interior
- * plus a (2*move + scan)-cell halo, 64-bit claim keys of the interior plus a
- * move-cell halo, and a byte per interior cell in LDS. SIM_EINVAL if ranges
- * are not set or the shape does not fit. sim_get_range_tiling writes
- * {cols, rows, threads}. */
-int sim_set_range_tiling(sim_handle* h, int32_t cols, int32_t rows, int32_t threads);
-int sim_get_range_tiling(sim_handle* h, int32_t out[3]);
+ * interiors of cols (16..256) x rows (8..256) cells advanced steps_per_launch
+ * (1..4) steps per launch, `threads` per workgroup (multiple of 64, <= 512).
+ * With R1 = 2*move + scan (the reach of one step) and k steps per launch, the
+ * workgroup keeps in LDS the codes of the interior plus k*R1 cells, the ids
+ * (and for ACO both pheromone planes) of the interior plus (k-1)*R1 + 3*move,
+ * a request byte and an agent list entry per cell of the interior plus
+ * (k-1)*R1 + 2*move, and a 64-bit claim key and a claim count per cell of the
+ * interior plus (k-1)*R1 + move. SIM_EINVAL if ranges are not set or the
+ * shape does not fit. sim_get_range_tiling writes {cols, rows,
+ * steps_per_launch, threads}. */
+int sim_set_range_tiling(sim_handle* h, int32_t cols, int32_t rows, int32_t steps_per_launch, int32_t threads);
+int sim_get_range_tiling(sim_handle* h, int32_t out[4]);
 
 /* Host-only: the ACO heuristic weights eta of sim_set_ranges for free runs
  * f = 1..8 (entry f-1; 0 for f > scan): diagonal[] for FD rays, lateral[]

@@ -49,13 +49,13 @@ BATCH_CANDIDATES = [
     (3, 62, 3, 256, 4),
 ]
 
-# (cols, rows, threads) of the range kernel (larger scanning and moving
-# ranges, one step per launch)
+# (cols, rows, steps per launch, threads) of the range kernel (larger scanning
+# and moving ranges); shapes that do not fit a workload's ranges are skipped
 RANGE_CANDIDATES = [
-    (64, 16, 256), (64, 24, 256), (64, 32, 256), (64, 48, 256), (64, 64, 256), (64, 32, 512),
-    (64, 64, 512), (128, 16, 256), (128, 32, 256), (128, 32, 512), (32, 32, 256), (32, 16, 128),
-    (48, 32, 256), (96, 32, 256), (64, 16, 512), (128, 16, 512), (64, 24, 512), (32, 32, 512),
-    (96, 16, 512), (48, 48, 512),
+    (64, 32, 1, 512), (64, 16, 1, 512), (64, 32, 1, 256), (64, 16, 1, 256), (128, 16, 1, 512),
+    (32, 32, 1, 512), (64, 24, 1, 512), (64, 32, 2, 512), (64, 16, 2, 512), (64, 24, 2, 512),
+    (32, 32, 2, 512), (48, 32, 2, 512), (64, 16, 3, 512), (32, 16, 3, 512), (64, 32, 2, 256),
+    (96, 16, 2, 512), (32, 32, 3, 512), (64, 8, 4, 512),
 ]
 
 _cache: Dict[str, tuple] = {}
@@ -112,7 +112,7 @@ def cached_batch(scns: Sequence) -> Optional[tuple]:
 
 
 def cached_range(scn, mode: int) -> Optional[tuple]:
-    """The cached (cols, rows, threads) of the range kernel for `scn`, if any."""
+    """The cached (cols, rows, steps per launch, threads) of the range kernel for `scn`, if any."""
     _ensure_loaded()
     if getattr(scn, "ranges", None) is None:
         return None
@@ -157,7 +157,7 @@ def tune_plain(scn, mode: int, steps: Optional[int] = None, candidates: Iterable
 
 def tune_range(scn, mode: int, steps: Optional[int] = None, candidates: Iterable = RANGE_CANDIDATES,
                device: str = "cuda") -> Tuple[tuple, List[tuple]]:
-    """Fastest range-kernel tiling (cols, rows, threads) for one scenario with
+    """Fastest range-kernel tiling (cols, rows, steps per launch, threads) for one scenario with
     ranges, each candidate timed over the same `steps` from the initial
     state. Returns (best, [(seconds, tiling)]) and caches best."""
     steps = steps or scn.steps or 100
@@ -170,7 +170,7 @@ def tune_range(scn, mode: int, steps: Optional[int] = None, candidates: Iterable
         except pedsim.SimError:
             warm.close()
             continue
-        warm.step(1, mode)  # loads the kernel
+        warm.step(tl[2], mode)  # loads the kernel
         warm.close()
         sim = pedsim.Sim(scn, device=device, autotune=False)
         sim.set_range_tiling(*tl)

@@ -172,7 +172,7 @@ struct sim_handle {
   // otherwise LEM and ACO steps run the range kernel with these ranges on
   // tiles of range_cols x range_rows cells, range_threads per workgroup.
   int scan, move;
-  int range_cols, range_rows, range_threads;
+  int range_cols, range_rows, range_steps, range_threads;
   float range_eta[2][kRangeMax];
 };
 
@@ -227,29 +227,33 @@ static void fill_range_eta(int S, int M, int beta, float out[2][kRangeMax]) {
 }
 
 // Range tiling is valid when the interior is at least 16 x 8 (bounds the
-// per-tile counters) and the workgroup's LDS fits.
-static bool range_tiling_valid(int cols, int rows, int threads, int S, int M) {
+// per-tile counters), the steps per launch are 1..4 and the workgroup's LDS
+// fits.
+static bool range_tiling_valid(int cols, int rows, int steps, int threads, int S, int M) {
   if (cols < kMinInteriorX || cols > 256 || rows < kMinInteriorY || rows > 256) return false;
+  if (steps < 1 || steps > kRangeMaxSteps) return false;
   if (threads < 64 || threads > kRangeMaxThreads || threads % 64) return false;
-  return RangeLayout{cols, rows, S, M, true}.bytes() <= (size_t)max_dynamic_lds();
+  return RangeLayout{cols, rows, S, M, steps, true}.bytes() <= (size_t)max_dynamic_lds();
 }
 
-// Default range tiling: 64 x 32 interiors (shorter where the LDS of long
-// ranges does not fit), 512 threads per workgroup.
+// Default range tiling: 64 x 32 interiors, two steps per launch where the
+// LDS allows, 512 threads per workgroup; smaller shapes for long ranges.
 static bool default_range_tiling(sim_handle* h) {
-  static const int shapes[][2] = {{64, 32}, {64, 16}, {64, 8}, {32, 16}, {32, 8}, {16, 8}};
+  static const int shapes[][3] = {{64, 32, 2}, {64, 16, 2}, {64, 32, 1}, {64, 16, 1}, {64, 8, 1},
+                                  {32, 16, 1}, {32, 8, 1},  {16, 8, 1}};
   for (const auto& sh : shapes)
-    if (range_tiling_valid(sh[0], sh[1], 512, h->scan, h->move)) {
+    if (range_tiling_valid(sh[0], sh[1], sh[2], 512, h->scan, h->move)) {
       h->range_cols = sh[0];
       h->range_rows = sh[1];
+      h->range_steps = sh[2];
       h->range_threads = 512;
       return true;
     }
   return false;
 }
 
-// One range launch per step, ping-ponging between the caller's planes and
-// the shadow copy like the tile engines.
+// Range launches of up to range_steps steps each, ping-ponging between the
+// caller's planes and the shadow copy like the tile engines.
 int run_range_steps(sim_handle* h, int mode, int32_t nsteps, hipStream_t s, hipEvent_t* ev, double* ms,
                     int64_t* launches) {
   const size_t cells = (size_t)h->p.W * (size_t)h->p.H;
@@ -274,28 +278,37 @@ int run_range_steps(sim_handle* h, int mode, int32_t nsteps, hipStream_t s, hipE
   P.tile_stats = h->stats;
   memcpy(P.eta, h->range_eta, sizeof(P.eta));
   Planes src = h->user, dst = h->shadow;
-  for (int32_t j = 0; j < nsteps; ++j) {
-    P.code_in = src.code;
-    P.id_in = src.id;
-    P.tau_in = aco ? src.tau : nullptr;
-    P.code_out = dst.code;
-    P.id_out = dst.id;
-    P.tau_out = aco ? dst.tau : nullptr;
-    P.t = h->t;
-    if (ev) (void)hipEventRecord(ev[0], s);
-    PEDSIM_HIP(launch_range(P, mode, h->range_threads, j == nsteps - 1, s));
-    if (ev) {
-      (void)hipEventRecord(ev[1], s);
-      PEDSIM_HIP(hipEventSynchronize(ev[1]));
-      float f = 0.0f;
-      (void)hipEventElapsedTime(&f, ev[0], ev[1]);
-      ms[0] += f;
-      launches[0] += 1;
+  int chunk[64];
+  int done = 0;
+  while (done < nsteps) {
+    const int remain = nsteps - done;
+    const int span = remain < 62 * h->range_steps ? remain : 62 * h->range_steps;
+    const int n = plan(span, h->range_steps, chunk, 64);
+    for (int j = 0; j < n; ++j) {
+      P.code_in = src.code;
+      P.id_in = src.id;
+      P.tau_in = aco ? src.tau : nullptr;
+      P.code_out = dst.code;
+      P.id_out = dst.id;
+      P.tau_out = aco ? dst.tau : nullptr;
+      P.t = h->t;
+      const bool last = done + chunk[j] == nsteps;
+      if (ev) (void)hipEventRecord(ev[0], s);
+      PEDSIM_HIP(launch_range(P, mode, h->range_threads, chunk[j], last, s));
+      if (ev) {
+        (void)hipEventRecord(ev[1], s);
+        PEDSIM_HIP(hipEventSynchronize(ev[1]));
+        float f = 0.0f;
+        (void)hipEventElapsedTime(&f, ev[0], ev[1]);
+        ms[0] += f;
+        launches[0] += 1;
+      }
+      h->t += (uint64_t)chunk[j];
+      done += chunk[j];
+      const Planes tmp = src;
+      src = dst;
+      dst = tmp;
     }
-    h->t += 1;
-    const Planes tmp = src;
-    src = dst;
-    dst = tmp;
   }
   if (src.code != h->user.code) {  // odd number of launches: state is in the shadow planes
     if (ev) (void)hipEventRecord(ev[0], s);
@@ -401,7 +414,7 @@ int init_handle(sim_handle* h, const sim_params* p, uint8_t* d_code, uint32_t* d
   h->tiling[kModeAco] = default_tiling(kModeAco, cells);
   h->tiling[kModeAcoTour] = default_tiling(kModeAcoTour, cells);
   h->scan = h->move = 0;
-  h->range_cols = h->range_rows = h->range_threads = 0;
+  h->range_cols = h->range_rows = h->range_steps = h->range_threads = 0;
   memset(h->range_eta, 0, sizeof(h->range_eta));
   PEDSIM_HIP(launch_count(d_code, p->W, p->H, p->cross_a, p->cross_b, h->stats, &h->stats_entries, s));
   PEDSIM_HIP(hipStreamSynchronize(s));
@@ -543,20 +556,22 @@ int sim_set_ranges(sim_handle* h, int32_t scan, int32_t move) {
   return SIM_OK;
 }
 
-int sim_set_range_tiling(sim_handle* h, int32_t cols, int32_t rows, int32_t threads) {
+int sim_set_range_tiling(sim_handle* h, int32_t cols, int32_t rows, int32_t steps_per_launch, int32_t threads) {
   if (!h || !h->scan) return SIM_EINVAL;
-  if (!range_tiling_valid(cols, rows, threads, h->scan, h->move)) return SIM_EINVAL;
+  if (!range_tiling_valid(cols, rows, steps_per_launch, threads, h->scan, h->move)) return SIM_EINVAL;
   h->range_cols = cols;
   h->range_rows = rows;
+  h->range_steps = steps_per_launch;
   h->range_threads = threads;
   return SIM_OK;
 }
 
-int sim_get_range_tiling(sim_handle* h, int32_t out[3]) {
+int sim_get_range_tiling(sim_handle* h, int32_t out[4]) {
   if (!h || !out || !h->scan) return SIM_EINVAL;
   out[0] = h->range_cols;
   out[1] = h->range_rows;
-  out[2] = h->range_threads;
+  out[2] = h->range_steps;
+  out[3] = h->range_threads;
   return SIM_OK;
 }
 

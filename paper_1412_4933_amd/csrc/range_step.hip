@@ -15,22 +15,28 @@
 //     among the agents landing on it; eq. 3 then eq. 4 on every cell.
 // With S = M = 1 this is the base step bit for bit.
 //
-// A tile is an interior of TX x TY cells. The new state of an interior cell
-// depends on the requests of agents up to 2M cells away (the contest at its
-// own cell, or at the target of its agent, up to M away, among requesters up
-// to M from that target), and those requests read cells up to S further out,
-// so the workgroup stages the code plane with a halo of 2M + S. Phases:
-//   1. stage codes (outside the grid counts as wall); clear the claim keys;
-//   2. request: every agent up to 2M from the interior scans its rays in LDS,
-//      chooses, draws its Philox words (the ticket is word 0) and claims its
-//      landing cell with a 64-bit LDS atomic min of
-//      (word 0 << 32 | agent number << 1 | group - 1) -- min is commutative,
-//      so the winner never depends on thread order; landing cells more than
-//      M from the interior are not needed and not claimed;
-//   3. commit + pheromone + counters over the interior: an empty cell with a
-//      claim takes the winner's group and id from its key; an agent whose
-//      landing cell's key names it leaves; both planes evaporate and gain the
-//      deposit where their group stands after the step.
+// A tile is an interior of TX x TY cells advanced k steps per launch. The new
+// state of a cell depends on cells up to R1 = 2M + S away (the contest at its
+// own cell, or at the landing cell of its agent, up to M away, among
+// claimants up to M from that cell, whose rays reach S further), so after
+// step j of a launch the state is needed exactly on the interior grown by
+// (k-1-j) R1 cells, and the workgroup stages the codes of the interior grown
+// by k R1 (ids and pheromone by (k-1) R1 + 3M, all it will read). Each step:
+//   1. list the agents up to (k-1-j) R1 + 2M from the interior (a wave ballot
+//      and one LDS atomic per wave);
+//   2. requests: every listed agent scans its rays in LDS and chooses (the
+//      forward ray without a draw; a side ray by eq. 1 or eq. 2 with its
+//      Philox words 1 and 2); every landing cell counts its claims;
+//   3. resolve: a landing cell with one claim goes to its claimant, one with
+//      several to the lowest (Philox word 0, agent number), by a 64-bit LDS
+//      atomic min of (word 0 << 32 | agent number << 1 | group - 1) -- min is
+//      commutative, so the winner never depends on thread order;
+//   4. commit on the interior grown by (k-1-j) R1: an empty cell with a claim
+//      takes the winner's group and id from its key, an agent whose landing
+//      cell's key names it leaves, both planes evaporate and gain the deposit
+//      where their group stands after the step. A cell's new value depends
+//      only on its own old value and the keys, so the commit is done in place
+//      in LDS; after the last step the interior goes to the output planes.
 // Reads one copy of the planes and writes the other (the caller's planes and
 // the scratch shadow ping-pong), since a tile's halo is its neighbours'
 // interior.
@@ -135,47 +141,48 @@ __device__ __forceinline__ int lanes_below_range(uint64_t bal) {
 }
 
 template <int MODE, int S>
-__global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P, int last) {
+__global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P, int steps, int last) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int ntiles = P.tiles_x * P.tiles_y;
   const int tile = range_tile_of_block(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
   const int TX = P.TX, TY = P.TY, M = P.M;
-  const int hc = 2 * M + S;  // code halo
+  const int R1 = 2 * M + S;  // reach of one step
+  // halos of the arrays (cells beyond the interior), fixed for the launch
+  const int hc = steps * R1;            // codes
+  const int hp = (steps - 1) * R1 + 3 * M;  // ids and pheromone
+  const int hr = (steps - 1) * R1 + 2 * M;  // request bytes
+  const int hk = (steps - 1) * R1 + M;      // claim keys and counts
   const int CW = TX + 2 * hc, CH = TY + 2 * hc;
-  const int RW = TX + 4 * M, RH = TY + 4 * M;  // request region: agents up to 2M from the interior
-  const int KW = TX + 2 * M, KH = TY + 2 * M;  // claim keys: cells up to M from the interior
-  const int PW = TX + 6 * M, PH = TY + 6 * M;  // pheromone: cells up to 3M from the interior
-  const RangeLayout L{TX, TY, S, M, MODE != kModeLem};
+  const int PW = TX + 2 * hp, PH = TY + 2 * hp;
+  const int RW = TX + 2 * hr, RH = TY + 2 * hr;
+  const int KW = TX + 2 * hk, KH = TY + 2 * hk;
+  const RangeLayout L{TX, TY, S, M, steps, MODE != kModeLem};
   uint8_t* code = smem + L.code();
   uint32_t* ids = (uint32_t*)(smem + L.ids());
-  uint8_t* rq = smem + L.req();                    // request byte per request-region cell
-  uint16_t* list = (uint16_t*)(smem + L.list());   // the request region's agents, compacted
+  uint8_t* rq = smem + L.req();
+  uint16_t* list = (uint16_t*)(smem + L.list());
   unsigned long long* keys = (unsigned long long*)(smem + L.keys());
-  uint32_t* claims = (uint32_t*)(smem + L.claims());  // claims per key-region cell
-  uint32_t* cnt = (uint32_t*)(smem + L.ctl());     // [0..4] counters, [5] agents in the list
-  float* eta_s = (float*)(cnt + 8);                // eta^beta: [0 lateral, 1 diagonal][free run - 1]
-  float* tau_a = (float*)(smem + L.tau());         // ACO: [PH][PW] per plane
+  uint32_t* claims = (uint32_t*)(smem + L.claims());
+  uint32_t* cnt = (uint32_t*)(smem + L.ctl());  // [0..4] counters, [5] agents in the list
+  float* eta_s = (float*)(cnt + 8);             // eta^beta: [0 lateral, 1 diagonal][free run - 1]
+  float* tau_a = (float*)(smem + L.tau());      // ACO: [PH][PW] per plane
   float* tau_b = tau_a + (size_t)PW * PH;
 
   const int x0 = (tile % P.tiles_x) * TX, y0 = (tile / P.tiles_x) * TY;
   const int W = P.W, H = P.H;
   const int lane = threadIdx.x & 63;
   const int nthreads = blockDim.x;
-  const uint32_t mc = div_magic((uint32_t)CW), mr = div_magic((uint32_t)RW), mp = div_magic((uint32_t)PW);
 
-  // 1. stage the codes of the region (interior + 2M + S; outside the grid
-  //    reads as wall), the ids of the request region and, for ACO, both
-  //    pheromone planes of the interior + 3M (every landing cell of a
-  //    requester and every interior cell); clear the keys and claim counts.
-  //    Every load of a round is issued before the round's LDS stores.
+  // 1. stage the codes (outside the grid reads as wall), the ids and, for
+  //    ACO, both pheromone planes; every load of a round is issued before the
+  //    round's LDS stores
   {
+    const uint32_t mc = div_magic((uint32_t)CW), mp = div_magic((uint32_t)PW);
     const size_t plane = (size_t)W * H;
     const int per = nthreads * kStageBatch;
-    const int rounds_c = (CW * CH + per - 1) / per, rounds_i = (RW * RH + per - 1) / per;
-    const int rounds_p = MODE != kModeLem ? (PW * PH + per - 1) / per : 0;
-    const int rounds = rounds_c > rounds_i ? (rounds_c > rounds_p ? rounds_c : rounds_p)
-                                           : (rounds_i > rounds_p ? rounds_i : rounds_p);
+    const int rounds_c = (CW * CH + per - 1) / per, rounds_p = (PW * PH + per - 1) / per;
+    const int rounds = rounds_c > rounds_p ? rounds_c : rounds_p;
     for (int rd = 0; rd < rounds; ++rd) {
       const int i0 = rd * per + threadIdx.x;
       uint32_t vc[kStageBatch], vi[kStageBatch];
@@ -190,218 +197,248 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
                                                                             : (uint32_t)kWall;
         }
         {
-          const int r = fast_div(i, mr), c = i - r * RW;
-          const int gx = x0 - 2 * M + c, gy = y0 - 2 * M + r;
-          vi[u] = (i < RW * RH && gx >= 0 && gx < W && gy >= 0 && gy < H) ? P.id_in[(size_t)gy * W + gx] : 0u;
-        }
-        if (MODE != kModeLem) {
           const int r = fast_div(i, mp), c = i - r * PW;
-          const int gx = x0 - 3 * M + c, gy = y0 - 3 * M + r;
+          const int gx = x0 - hp + c, gy = y0 - hp + r;
           const bool in = i < PW * PH && gx >= 0 && gx < W && gy >= 0 && gy < H;
           const size_t gi = in ? (size_t)gy * W + gx : 0;
-          va[u] = in ? P.tau_in[gi] : 0.0f;
-          vb[u] = in ? P.tau_in[plane + gi] : 0.0f;
+          vi[u] = in ? P.id_in[gi] : 0u;
+          if (MODE != kModeLem) {
+            va[u] = in ? P.tau_in[gi] : 0.0f;
+            vb[u] = in ? P.tau_in[plane + gi] : 0.0f;
+          }
         }
       }
 #pragma unroll
       for (int u = 0; u < kStageBatch; ++u) {
         const int i = i0 + u * nthreads;
         if (i < CW * CH) code[i] = (uint8_t)vc[u];
-        if (i < RW * RH) ids[i] = vi[u];
-        if (MODE != kModeLem && i < PW * PH) {
-          tau_a[i] = va[u];
-          tau_b[i] = vb[u];
-        }
-      }
-    }
-    for (int i = threadIdx.x; i < KW * KH; i += nthreads) {
-      keys[i] = kNoClaim;
-      claims[i] = 0u;
-    }
-    if (threadIdx.x < 8) cnt[threadIdx.x] = 0u;
-    if (threadIdx.x < 2 * kRangeMax) eta_s[threadIdx.x] = P.eta[threadIdx.x / kRangeMax][threadIdx.x % kRangeMax];
-  }
-  __syncthreads();
-
-  // 2. list the agents of the request region (one LDS atomic per wave); clear
-  //    every cell's request
-  for (int i0 = threadIdx.x - lane; i0 < RW * RH; i0 += nthreads) {
-    const int i = i0 + lane;
-    bool agent = false;
-    if (i < RW * RH) {
-      const int r = fast_div(i, mr), c = i - r * RW;
-      const int g = code[(r + S) * CW + c + S];
-      agent = g == kGroupA || g == kGroupB;
-      rq[i] = 0u;
-    }
-    const uint64_t bal = __ballot(agent);
-    if (bal) {
-      uint32_t base = 0u;
-      if (lane == 0) base = atomicAdd(&cnt[5], (uint32_t)__popcll(bal));
-      base = __shfl(base, 0);
-      if (agent) list[base + lanes_below_range(bal)] = (uint16_t)i;
-    }
-  }
-  __syncthreads();
-  const int n_agents = (int)cnt[5];
-
-  // 3. requests: every listed agent scans its rays in LDS and chooses (the
-  //    forward ray without a draw; a side ray by eq. 1 or eq. 2 with the
-  //    agent's Philox words 1 and 2); every landing cell counts its claims
-  for (int t = threadIdx.x; t < n_agents; t += nthreads) {
-    const int i = list[t];
-    const int r = fast_div(i, mr), c = i - r * RW;
-    const int cx = c + S, cy = r + S;  // code-region coordinates
-    const int g = code[cy * CW + cx];
-    const int d = g == kGroupA ? 1 : -1;
-    const int at = cy * CW + cx;
-    // the cell next to the agent on each ray first: an agent with all five
-    // blocked (most of a jam) makes no request
-    uint32_t first[5];
-#pragma unroll
-    for (int ray = 0; ray < 5; ++ray) first[ray] = code[at + ray_dy(ray) * CW + ray_dx(ray, d)];
-    if (first[0] != kEmpty && first[1] != kEmpty && first[2] != kEmpty && first[3] != kEmpty &&
-        first[4] != kEmpty)
-      continue;
-    int f[5], d2[5];
-    bool side = false;
-#pragma unroll
-    for (int ray = 0; ray < 5; ++ray) {
-      const int ux = ray_dx(ray, d), uy = ray_dy(ray);
-      // the rest of the ray read at once (independent LDS loads), the free
-      // run counted afterwards
-      const int step = uy * CW + ux;
-      uint32_t v[S];
-      v[0] = first[ray];
-#pragma unroll
-      for (int j = 1; j < S; ++j) v[j] = code[at + (j + 1) * step];
-      int j = 0;
-      bool open = true;
-#pragma unroll
-      for (int q = 0; q < S; ++q) {
-        open = open && v[q] == kEmpty;
-        j += open ? 1 : 0;
-      }
-      f[ray] = j;
-      const int k = j < M ? j : M;
-      const int a = ray <= 2 ? 1 : 0;
-      const int b = ray == 0 ? 0 : 1;
-      const int dx = M + 1 - a * k;
-      d2[ray] = dx * dx + b * k * k;
-      side |= ray > 0 && j >= 1;
-    }
-    int choice = -1;
-    if (f[0] >= 1) {
-      choice = 0;
-    } else if (side) {
-      const Words w = agent_words(ids[i] - 1u, P.t, P.key0, P.key1);
-      if (MODE == kModeLem) {
-        choice = range_lem(f, d2, w.w1, w.w2);
-      } else {
-        const int px = c + M, py = r + M;  // the agent in pheromone-region coordinates
-        const float* tp = g == kGroupA ? tau_a : tau_b;
-        float tau[5], eta[5];
-#pragma unroll
-        for (int ray = 1; ray <= 4; ++ray) {
-          tau[ray] = 0.0f;
-          eta[ray] = 0.0f;
-          if (f[ray] >= 1) {
-            const int k = f[ray] < M ? f[ray] : M;
-            eta[ray] = eta_s[(ray <= 2 ? kRangeMax : 0) + f[ray] - 1];
-            tau[ray] = tp[(py + k * ray_dy(ray)) * PW + px + k * ray_dx(ray, d)];
+        if (i < PW * PH) {
+          ids[i] = vi[u];
+          if (MODE != kModeLem) {
+            tau_a[i] = va[u];
+            tau_b[i] = vb[u];
           }
         }
-        choice = range_aco(f, d2, tau, eta, P.alpha, w.w1, w.w2);
       }
     }
-    if (choice >= 0) {
-      const int len = f[choice] < M ? f[choice] : M;
-      rq[i] = (uint8_t)((choice + 1) | (len << 3));
-      // landing cell in key-region coordinates; farther ones are not needed
-      const int kx = c - M + len * ray_dx(choice, d), ky = r - M + len * ray_dy(choice);
-      if (kx >= 0 && kx < KW && ky >= 0 && ky < KH) atomicAdd(&claims[ky * KW + kx], 1u);
-    }
+    if (threadIdx.x < 2 * kRangeMax) eta_s[threadIdx.x] = P.eta[threadIdx.x / kRangeMax][threadIdx.x % kRangeMax];
+    if (threadIdx.x < 8) cnt[threadIdx.x] = 0u;
   }
-  __syncthreads();
 
-  // 4. resolve: a landing cell with one claim goes to its claimant; one with
-  //    several to the lowest (Philox word 0, agent number), by a 64-bit LDS
-  //    atomic min of (word 0 << 32 | agent number << 1 | group - 1), whatever
-  //    the order of the claims
-  for (int t = threadIdx.x; t < n_agents; t += nthreads) {
-    const int i = list[t];
-    const int q = rq[i];
-    if (!q) continue;
-    const int r = fast_div(i, mr), c = i - r * RW;
-    const int g = code[(r + S) * CW + c + S];
-    const int ray = (q & 7) - 1, len = q >> 3;
-    const int d = g == kGroupA ? 1 : -1;
-    const int kx = c - M + len * ray_dx(ray, d), ky = r - M + len * ray_dy(ray);
-    if (kx < 0 || kx >= KW || ky < 0 || ky >= KH) continue;
-    const int ki = ky * KW + kx;
-    const uint32_t k_agent = ids[i] - 1u;
-    const unsigned long long who = ((unsigned long long)k_agent << 1) | (unsigned long long)(g - 1);
-    if (claims[ki] == 1u) {
-      keys[ki] = who;
-    } else {
-      const uint32_t w0 = agent_words(k_agent, P.t, P.key0, P.key1).w0;
-      atomicMin(&keys[ki], ((unsigned long long)w0 << 32) | who);
-    }
-  }
-  __syncthreads();
-
-  // 5. commit, pheromone (eq. 3 then eq. 4) and counters over the interior
   uint32_t n_a = 0, n_b = 0, c_a = 0, c_b = 0, moved = 0;
-  const size_t plane = (size_t)W * H;
-  {
-    const uint32_t mt = div_magic((uint32_t)TX);
-    for (int i = threadIdx.x; i < TX * TY; i += nthreads) {
-      const int iy = fast_div(i, mt), ix = i - iy * TX;
+  for (int j = 0; j < steps; ++j) {
+    const uint64_t t = P.t + (uint64_t)j;
+    const int grow = (steps - 1 - j) * R1;  // the state after this step is needed on the interior grown by it
+    // this step's windows, as [lo, lo + width) in each array's coordinates
+    const int rlo = hr - (grow + 2 * M), rw = TX + 2 * (grow + 2 * M), rh = TY + 2 * (grow + 2 * M);
+    const int klo = hk - (grow + M), kw = TX + 2 * (grow + M), kh = TY + 2 * (grow + M);
+    const uint32_t mrw = div_magic((uint32_t)rw), mkw = div_magic((uint32_t)kw);
+
+    // clear the claims of this step's key window (the previous step's commit
+    // has passed its barrier)
+    for (int i = threadIdx.x; i < kw * kh; i += nthreads) {
+      const int r = fast_div(i, mkw), c = i - r * kw;
+      const int ki = (r + klo) * KW + c + klo;
+      keys[ki] = kNoClaim;
+      claims[ki] = 0u;
+    }
+    __syncthreads();  // staged state (first step) or committed state visible; counters cleared
+
+    // 2. list the agents of the request window; clear their cells' requests
+    for (int i0 = threadIdx.x - lane; i0 < rw * rh; i0 += nthreads) {
+      const int i = i0 + lane;
+      bool agent = false;
+      int ri = 0;
+      if (i < rw * rh) {
+        const int r = fast_div(i, mrw) + rlo, c = i - fast_div(i, mrw) * rw + rlo;
+        ri = r * RW + c;
+        const int g = code[(r + hc - hr) * CW + c + hc - hr];
+        agent = g == kGroupA || g == kGroupB;
+        rq[ri] = 0u;
+      }
+      const uint64_t bal = __ballot(agent);
+      if (bal) {
+        uint32_t base = 0u;
+        if (lane == 0) base = atomicAdd(&cnt[5], (uint32_t)__popcll(bal));
+        base = __shfl(base, 0);
+        if (agent) list[base + lanes_below_range(bal)] = (uint16_t)ri;
+      }
+    }
+    __syncthreads();
+    const int n_agents = (int)cnt[5];
+
+    // 3. requests of the listed agents; every landing cell counts its claims
+    const uint32_t mRW = div_magic((uint32_t)RW);
+    for (int q = threadIdx.x; q < n_agents; q += nthreads) {
+      const int ri = list[q];
+      const int r = fast_div(ri, mRW), c = ri - r * RW;  // request-array coordinates
+      const int cx = c + hc - hr, cy = r + hc - hr;     // code-array coordinates
+      const int at = cy * CW + cx;
+      const int g = code[at];
+      const int d = g == kGroupA ? 1 : -1;
+      // the cell next to the agent on each ray first: an agent with all five
+      // blocked (most of a jam) makes no request
+      uint32_t first[5];
+#pragma unroll
+      for (int ray = 0; ray < 5; ++ray) first[ray] = code[at + ray_dy(ray) * CW + ray_dx(ray, d)];
+      if (first[0] != kEmpty && first[1] != kEmpty && first[2] != kEmpty && first[3] != kEmpty &&
+          first[4] != kEmpty)
+        continue;
+      int f[5], d2[5];
+      bool side = false;
+#pragma unroll
+      for (int ray = 0; ray < 5; ++ray) {
+        const int ux = ray_dx(ray, d), uy = ray_dy(ray);
+        // the rest of the ray read at once (independent LDS loads), the free
+        // run counted afterwards
+        const int step = uy * CW + ux;
+        uint32_t v[S];
+        v[0] = first[ray];
+#pragma unroll
+        for (int jj = 1; jj < S; ++jj) v[jj] = code[at + (jj + 1) * step];
+        int run = 0;
+        bool open = true;
+#pragma unroll
+        for (int qq = 0; qq < S; ++qq) {
+          open = open && v[qq] == kEmpty;
+          run += open ? 1 : 0;
+        }
+        f[ray] = run;
+        const int k = run < M ? run : M;
+        const int a = ray <= 2 ? 1 : 0;
+        const int b = ray == 0 ? 0 : 1;
+        const int dx = M + 1 - a * k;
+        d2[ray] = dx * dx + b * k * k;
+        side |= ray > 0 && run >= 1;
+      }
+      const int px = c + hp - hr, py = r + hp - hr;  // id / pheromone-array coordinates
+      int choice = -1;
+      if (f[0] >= 1) {
+        choice = 0;
+      } else if (side) {
+        const Words w = agent_words(ids[py * PW + px] - 1u, t, P.key0, P.key1);
+        if (MODE == kModeLem) {
+          choice = range_lem(f, d2, w.w1, w.w2);
+        } else {
+          const float* tp = g == kGroupA ? tau_a : tau_b;
+          float tau[5], eta[5];
+#pragma unroll
+          for (int ray = 1; ray <= 4; ++ray) {
+            tau[ray] = 0.0f;
+            eta[ray] = 0.0f;
+            if (f[ray] >= 1) {
+              const int k = f[ray] < M ? f[ray] : M;
+              eta[ray] = eta_s[(ray <= 2 ? kRangeMax : 0) + f[ray] - 1];
+              tau[ray] = tp[(py + k * ray_dy(ray)) * PW + px + k * ray_dx(ray, d)];
+            }
+          }
+          choice = range_aco(f, d2, tau, eta, P.alpha, w.w1, w.w2);
+        }
+      }
+      if (choice >= 0) {
+        const int len = f[choice] < M ? f[choice] : M;
+        rq[ri] = (uint8_t)((choice + 1) | (len << 3));
+        // landing cell in key-array coordinates; outside this step's key window
+        // it is not needed
+        const int kx = c + hk - hr + len * ray_dx(choice, d), ky = r + hk - hr + len * ray_dy(choice);
+        if (kx >= klo && kx < klo + kw && ky >= klo && ky < klo + kh) atomicAdd(&claims[ky * KW + kx], 1u);
+      }
+    }
+    __syncthreads();
+
+    // 4. resolve: one claim goes to its claimant; several to the lowest
+    //    (Philox word 0, agent number)
+    for (int q = threadIdx.x; q < n_agents; q += nthreads) {
+      const int ri = list[q];
+      const int code_req = rq[ri];
+      if (!code_req) continue;
+      const int r = fast_div(ri, mRW), c = ri - r * RW;
+      const int g = code[(r + hc - hr) * CW + c + hc - hr];
+      const int ray = (code_req & 7) - 1, len = code_req >> 3;
+      const int d = g == kGroupA ? 1 : -1;
+      const int kx = c + hk - hr + len * ray_dx(ray, d), ky = r + hk - hr + len * ray_dy(ray);
+      if (kx < klo || kx >= klo + kw || ky < klo || ky >= klo + kh) continue;
+      const int ki = ky * KW + kx;
+      const uint32_t k_agent = ids[(r + hp - hr) * PW + c + hp - hr] - 1u;
+      const unsigned long long who = ((unsigned long long)k_agent << 1) | (unsigned long long)(g - 1);
+      if (claims[ki] == 1u) {
+        keys[ki] = who;
+      } else {
+        const uint32_t w0 = agent_words(k_agent, t, P.key0, P.key1).w0;
+        atomicMin(&keys[ki], ((unsigned long long)w0 << 32) | who);
+      }
+    }
+    __syncthreads();
+
+    // 5. commit on the interior grown by `grow`: in place in LDS, or (last
+    //    step) the interior to the output planes, with pheromone and counters
+    const bool final_step = j == steps - 1;
+    const int ew = TX + 2 * grow, eh = TY + 2 * grow;
+    const uint32_t mew = div_magic((uint32_t)ew);
+    const size_t plane = (size_t)W * H;
+    for (int i = threadIdx.x; i < ew * eh; i += nthreads) {
+      const int er = fast_div(i, mew), ec = i - er * ew;
+      const int ix = ec - grow, iy = er - grow;  // interior coordinates
       const int gx = x0 + ix, gy = y0 + iy;
-      if (gx >= W || gy >= H) continue;
-      const size_t gi = (size_t)gy * W + gx;
-      const int g0 = code[(iy + hc) * CW + ix + hc];
+      if (final_step && (gx >= W || gy >= H)) continue;
+      const int ci = (iy + hc) * CW + ix + hc;
+      const int pi = (iy + hp) * PW + ix + hp;
+      const int g0 = code[ci];
       int nc = g0;
       uint32_t nid = 0u;
       if (g0 == kEmpty) {
-        const unsigned long long key = keys[(iy + M) * KW + ix + M];
+        const unsigned long long key = keys[(iy + hk) * KW + ix + hk];
         if (key != kNoClaim) {
           nc = (int)(key & 1ull) + 1;
           nid = (uint32_t)((key >> 1) & 0x7fffffffull) + 1u;
-          moved += 1;
+          moved += final_step ? 1u : 0u;
         }
       } else if (g0 == kGroupA || g0 == kGroupB) {
-        const int ri = (iy + 2 * M) * RW + ix + 2 * M;
-        nid = ids[ri];
-        const int q = rq[ri];
-        if (q) {
-          const int ray = (q & 7) - 1, len = q >> 3;
+        nid = ids[pi];
+        const int code_req = rq[(iy + hr) * RW + ix + hr];
+        if (code_req) {
+          const int ray = (code_req & 7) - 1, len = code_req >> 3;
           const int d = g0 == kGroupA ? 1 : -1;
-          const int kx = ix + M + len * ray_dx(ray, d), ky = iy + M + len * ray_dy(ray);
-          const unsigned long long key = keys[ky * KW + kx];
+          const unsigned long long key =
+              keys[(iy + hk + len * ray_dy(ray)) * KW + ix + hk + len * ray_dx(ray, d)];
           if ((uint32_t)((key >> 1) & 0x7fffffffull) == nid - 1u) {
             nc = kEmpty;
             nid = 0u;
           }
         }
       }
-      P.code_out[gi] = (uint8_t)nc;
-      P.id_out[gi] = nid;
+      float va = 0.0f, vb = 0.0f;
       if (MODE != kModeLem) {
-        const int pi = (iy + 3 * M) * PW + ix + 3 * M;
-        float va = P.keep * tau_a[pi];
-        float vb = P.keep * tau_b[pi];
+        va = P.keep * tau_a[pi];
+        vb = P.keep * tau_b[pi];
         if (nc == kGroupA) va = va + P.dtau;
         if (nc == kGroupB) vb = vb + P.dtau;
-        P.tau_out[gi] = va;
-        P.tau_out[plane + gi] = vb;
       }
-      n_a += nc == kGroupA;
-      n_b += nc == kGroupB;
-      c_a += nc == kGroupA && gx >= W - P.cross_b;
-      c_b += nc == kGroupB && gx < P.cross_a;
+      if (!final_step) {
+        code[ci] = (uint8_t)nc;
+        ids[pi] = nid;
+        if (MODE != kModeLem) {
+          tau_a[pi] = va;
+          tau_b[pi] = vb;
+        }
+      } else {
+        const size_t gi = (size_t)gy * W + gx;
+        P.code_out[gi] = (uint8_t)nc;
+        P.id_out[gi] = nid;
+        if (MODE != kModeLem) {
+          P.tau_out[gi] = va;
+          P.tau_out[plane + gi] = vb;
+        }
+        n_a += nc == kGroupA;
+        n_b += nc == kGroupB;
+        c_a += nc == kGroupA && gx >= W - P.cross_b;
+        c_b += nc == kGroupB && gx < P.cross_a;
+      }
     }
+    if (threadIdx.x == 0) cnt[5] = 0u;  // the next step's list (read by everyone before the last barrier)
+    if (!final_step) __syncthreads();  // the commit's key reads and LDS writes before the next step
   }
+
   if (last) {
     // one LDS atomic per wave after a cross-lane sum
 #pragma unroll
@@ -425,8 +462,8 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
 }
 
 template <int MODE, int S>
-hipError_t launch_range_mode(const RangeScenario& P, int threads, int last, hipStream_t s) {
-  const size_t lds = RangeLayout{P.TX, P.TY, P.S, P.M, MODE != kModeLem}.bytes();
+hipError_t launch_range_mode(const RangeScenario& P, int threads, int steps, int last, hipStream_t s) {
+  const size_t lds = RangeLayout{P.TX, P.TY, P.S, P.M, steps, MODE != kModeLem}.bytes();
   static bool attr_done = false;
   if (!attr_done) {
     (void)hipFuncSetAttribute((const void*)range_kernel<MODE, S>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -436,31 +473,31 @@ hipError_t launch_range_mode(const RangeScenario& P, int threads, int last, hipS
   }
   const int ntiles = P.tiles_x * P.tiles_y;
   const int blocks = ((ntiles + 7) / 8) * 8;
-  range_kernel<MODE, S><<<blocks, threads, lds, s>>>(P, last);
+  range_kernel<MODE, S><<<blocks, threads, lds, s>>>(P, steps, last);
   return hipGetLastError();
 }
 
 template <int MODE>
-hipError_t launch_range_scan(const RangeScenario& P, int threads, int last, hipStream_t s) {
+hipError_t launch_range_scan(const RangeScenario& P, int threads, int steps, int last, hipStream_t s) {
   switch (P.S) {
-    case 1: return launch_range_mode<MODE, 1>(P, threads, last, s);
-    case 2: return launch_range_mode<MODE, 2>(P, threads, last, s);
-    case 3: return launch_range_mode<MODE, 3>(P, threads, last, s);
-    case 4: return launch_range_mode<MODE, 4>(P, threads, last, s);
-    case 5: return launch_range_mode<MODE, 5>(P, threads, last, s);
-    case 6: return launch_range_mode<MODE, 6>(P, threads, last, s);
-    case 7: return launch_range_mode<MODE, 7>(P, threads, last, s);
-    default: return launch_range_mode<MODE, 8>(P, threads, last, s);
+    case 1: return launch_range_mode<MODE, 1>(P, threads, steps, last, s);
+    case 2: return launch_range_mode<MODE, 2>(P, threads, steps, last, s);
+    case 3: return launch_range_mode<MODE, 3>(P, threads, steps, last, s);
+    case 4: return launch_range_mode<MODE, 4>(P, threads, steps, last, s);
+    case 5: return launch_range_mode<MODE, 5>(P, threads, steps, last, s);
+    case 6: return launch_range_mode<MODE, 6>(P, threads, steps, last, s);
+    case 7: return launch_range_mode<MODE, 7>(P, threads, steps, last, s);
+    default: return launch_range_mode<MODE, 8>(P, threads, steps, last, s);
   }
 }
 
 }  // namespace
 
-hipError_t launch_range(const RangeScenario& P, int mode, int threads, int last, hipStream_t s) {
+hipError_t launch_range(const RangeScenario& P, int mode, int threads, int steps, int last, hipStream_t s) {
   if (threads < 64 || threads > kRangeMaxThreads || threads % 64) return hipErrorInvalidValue;
-  if (P.S < 1 || P.S > kRangeMax || P.M < 1 || P.M > P.S) return hipErrorInvalidValue;
-  return mode == kModeLem ? launch_range_scan<kModeLem>(P, threads, last, s)
-                          : launch_range_scan<kModeAco>(P, threads, last, s);
+  if (P.S < 1 || P.S > kRangeMax || P.M < 1 || P.M > P.S || steps < 1) return hipErrorInvalidValue;
+  return mode == kModeLem ? launch_range_scan<kModeLem>(P, threads, steps, last, s)
+                          : launch_range_scan<kModeAco>(P, threads, steps, last, s);
 }
 
 }  // namespace pedsim

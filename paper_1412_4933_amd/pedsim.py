@@ -81,7 +81,7 @@ def lib() -> ctypes.CDLL:
         L.sim_attach_tour.argtypes = [vp, vp, vp, vp]
         L.sim_set_neighbours.argtypes = [vp, i32]
         L.sim_set_ranges.argtypes = [vp, i32, i32]
-        L.sim_set_range_tiling.argtypes = [vp, i32, i32, i32]
+        L.sim_set_range_tiling.argtypes = [vp, i32, i32, i32, i32]
         L.sim_get_range_tiling.argtypes = [vp, P(ctypes.c_int32)]
         L.sim_range_weights.argtypes = [i32, i32, i32, P(ctypes.c_float), P(ctypes.c_float)]
         L.sim_stats.argtypes = [vp, P(SimStats), vp]
@@ -190,12 +190,13 @@ def sim_set_ranges(h, scan: int, move: int) -> None:
     _check(lib().sim_set_ranges(h, int(scan), int(move)), "sim_set_ranges")
 
 
-def sim_set_range_tiling(h, cols: int, rows: int, threads: int) -> None:
-    _check(lib().sim_set_range_tiling(h, int(cols), int(rows), int(threads)), "sim_set_range_tiling")
+def sim_set_range_tiling(h, cols: int, rows: int, steps_per_launch: int, threads: int) -> None:
+    _check(lib().sim_set_range_tiling(h, int(cols), int(rows), int(steps_per_launch), int(threads)),
+           "sim_set_range_tiling")
 
 
 def sim_get_range_tiling(h):
-    out = (ctypes.c_int32 * 3)()
+    out = (ctypes.c_int32 * 4)()
     _check(lib().sim_get_range_tiling(h, out), "sim_get_range_tiling")
     return tuple(int(v) for v in out)
 
@@ -431,8 +432,8 @@ class Sim:
         self.ranges = None if scan == 0 else (int(scan), int(move))
         self.range_tuned = None
 
-    def set_range_tiling(self, cols: int, rows: int, threads: int) -> None:
-        sim_set_range_tiling(self.h, cols, rows, threads)
+    def set_range_tiling(self, cols: int, rows: int, steps_per_launch: int, threads: int) -> None:
+        sim_set_range_tiling(self.h, cols, rows, steps_per_launch, threads)
 
     def range_tiling(self):
         return sim_get_range_tiling(self.h)

@@ -55,7 +55,7 @@ def test_tune_range_winner_matches_oracle(tuner):
     from paper_1412_4933_amd import pedsim
     scn = S.make_scenario(260, 90, 2000, 2000, band_a=14, seed=62, mode=S.MODE_ACO, steps=40,
                           ranges=(4, 2))
-    cands = [(64, 16, 256), (64, 32, 256), (128, 32, 512), (32, 16, 128)]
+    cands = [(64, 16, 1, 256), (64, 32, 1, 256), (64, 32, 2, 512), (32, 16, 3, 128)]
     best, timings = tuner.tune_range(scn, S.MODE_ACO, candidates=cands)
     print("[gpu-case] tune_range:", best, [(round(t * 1e3, 3), tl) for t, tl in timings], flush=True)
     assert best in cands and len(timings) == len(cands)

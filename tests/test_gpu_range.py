@@ -92,19 +92,23 @@ def test_range_one_one_is_the_base_step(pedsim, mode):
     run_both(pedsim, scn, mode, (1, 1), chunks=(3, 20, 17), base_oracle=True)
 
 
-# launch shapes (interior cols, rows, threads); the longest ranges need the
-# most LDS per cell, so they get the smaller shapes
-TILINGS = [((3, 2), t) for t in [(16, 8, 64), (32, 8, 128), (64, 16, 256), (64, 32, 512), (128, 24, 256),
-                                   (48, 40, 192), (256, 8, 512), (64, 64, 256)]] + \
-          [((8, 8), t) for t in [(16, 8, 64), (32, 8, 128), (64, 16, 256), (32, 16, 512), (96, 8, 256),
-                                   (48, 40, 192), (24, 24, 320)]]
+# launch shapes (interior cols, rows, steps per launch, threads); the longest
+# ranges need the most LDS per cell, so they get the smaller shapes
+TILINGS = [((3, 2), t) for t in [(16, 8, 1, 64), (32, 8, 1, 128), (64, 16, 1, 256), (64, 32, 1, 512),
+                                   (128, 24, 1, 256), (48, 40, 1, 192), (256, 8, 1, 512), (64, 64, 1, 256),
+                                   (64, 32, 2, 512), (64, 16, 3, 512), (32, 16, 4, 256), (16, 8, 4, 64),
+                                   (48, 24, 2, 320)]] + \
+          [((8, 8), t) for t in [(16, 8, 1, 64), (32, 8, 1, 128), (64, 16, 1, 256), (32, 16, 1, 512),
+                                   (96, 8, 1, 256), (40, 24, 1, 192), (24, 24, 1, 320), (16, 16, 1, 128)]] + \
+          [((1, 1), t) for t in [(64, 32, 4, 512), (32, 8, 3, 128)]] + \
+          [((4, 2), t) for t in [(64, 32, 2, 512), (64, 24, 2, 256)]]
 
 
 @pytest.mark.parametrize("ranges,tiling", TILINGS)
 def test_range_tilings(pedsim, tiling, ranges):
     scn = S.make_scenario(333, 95, 2500, 2400, band_a=14, seed=5, mode=S.MODE_ACO, obstacle_frac=0.06)
     say("range tiling", tiling, ranges)
-    run_both(pedsim, scn, S.MODE_ACO, ranges, chunks=(1, 6, 9), tiling=tiling)
+    run_both(pedsim, scn, S.MODE_ACO, ranges, chunks=(1, 6, 9, 2, 5), tiling=tiling)
 
 
 @pytest.mark.parametrize("shape", [(3, 3), (5, 4), (7, 3), (1, 5), (9, 2), (65, 9), (64, 8), (130, 17)])
@@ -220,9 +224,13 @@ def test_range_rejections(pedsim):
     with pytest.raises(pedsim.SimError):
         pedsim.sim_set_neighbours(sim.h, 8)
     with pytest.raises(pedsim.SimError):
-        sim.set_range_tiling(8, 8, 256)
+        sim.set_range_tiling(8, 8, 1, 256)
     with pytest.raises(pedsim.SimError):
-        sim.set_range_tiling(64, 32, 100)
+        sim.set_range_tiling(64, 32, 1, 100)
+    with pytest.raises(pedsim.SimError):
+        sim.set_range_tiling(64, 32, 5, 256)
+    with pytest.raises(pedsim.SimError):
+        sim.set_range_tiling(64, 32, 0, 256)
     sim.close()
 
 
