@@ -127,7 +127,7 @@ __device__ __forceinline__ int range_aco(const int f[5], const int d2[5], const 
 }
 
 constexpr unsigned long long kNoClaim = ~0ull;
-constexpr int kStageBatch = 8;  // global loads a thread keeps in flight while staging
+constexpr int kStageBatch = 16;  // cells whose global loads a thread keeps in flight while staging
 
 // q = i / d for i * d < 2^32, with m = ceil(2^32 / d): one multiply-high.
 __device__ __forceinline__ uint32_t div_magic(uint32_t d) {
@@ -175,48 +175,43 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
   const int nthreads = blockDim.x;
 
   // 1. stage the codes (outside the grid reads as wall), the ids and, for
-  //    ACO, both pheromone planes; every load of a round is issued before the
-  //    round's LDS stores
+  //    ACO, both pheromone planes (whose array is a sub-rectangle of the code
+  //    array): cells dealt to the threads in row-major order, kStageBatch
+  //    cells' loads in flight before their LDS stores
   {
-    const uint32_t mc = div_magic((uint32_t)CW), mp = div_magic((uint32_t)PW);
+    const int off = hc - hp;  // the pheromone array's origin in code-array coordinates
     const size_t plane = (size_t)W * H;
-    const int per = nthreads * kStageBatch;
-    const int rounds_c = (CW * CH + per - 1) / per, rounds_p = (PW * PH + per - 1) / per;
-    const int rounds = rounds_c > rounds_p ? rounds_c : rounds_p;
-    for (int rd = 0; rd < rounds; ++rd) {
-      const int i0 = rd * per + threadIdx.x;
+    const uint32_t mc = div_magic((uint32_t)CW);
+    for (int i0 = threadIdx.x; i0 < CW * CH; i0 += nthreads * kStageBatch) {
       uint32_t vc[kStageBatch], vi[kStageBatch];
       float va[kStageBatch], vb[kStageBatch];
+      int pi[kStageBatch];
 #pragma unroll
       for (int u = 0; u < kStageBatch; ++u) {
         const int i = i0 + u * nthreads;
-        {
-          const int r = fast_div(i, mc), c = i - r * CW;
-          const int gx = x0 - hc + c, gy = y0 - hc + r;
-          vc[u] = (i < CW * CH && gx >= 0 && gx < W && gy >= 0 && gy < H) ? P.code_in[(size_t)gy * W + gx]
-                                                                            : (uint32_t)kWall;
-        }
-        {
-          const int r = fast_div(i, mp), c = i - r * PW;
-          const int gx = x0 - hp + c, gy = y0 - hp + r;
-          const bool in = i < PW * PH && gx >= 0 && gx < W && gy >= 0 && gy < H;
-          const size_t gi = in ? (size_t)gy * W + gx : 0;
-          vi[u] = in ? P.id_in[gi] : 0u;
-          if (MODE != kModeLem) {
-            va[u] = in ? P.tau_in[gi] : 0.0f;
-            vb[u] = in ? P.tau_in[plane + gi] : 0.0f;
-          }
+        const int r = fast_div(i, mc), c = i - r * CW;
+        const int gx = x0 - hc + c, gy = y0 - hc + r;
+        const bool in = i < CW * CH && gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const int pr = r - off, pc = c - off;
+        const bool pin = pr >= 0 && pr < PH && pc >= 0 && pc < PW;  // (i < CW * CH follows)
+        pi[u] = pin ? pr * PW + pc : -1;
+        const size_t gi = in ? (size_t)gy * W + gx : 0;
+        vc[u] = in ? P.code_in[gi] : (uint32_t)kWall;
+        vi[u] = in && pin ? P.id_in[gi] : 0u;
+        if (MODE != kModeLem) {
+          va[u] = in && pin ? P.tau_in[gi] : 0.0f;
+          vb[u] = in && pin ? P.tau_in[plane + gi] : 0.0f;
         }
       }
 #pragma unroll
       for (int u = 0; u < kStageBatch; ++u) {
         const int i = i0 + u * nthreads;
         if (i < CW * CH) code[i] = (uint8_t)vc[u];
-        if (i < PW * PH) {
-          ids[i] = vi[u];
+        if (pi[u] >= 0) {
+          ids[pi[u]] = vi[u];
           if (MODE != kModeLem) {
-            tau_a[i] = va[u];
-            tau_b[i] = vb[u];
+            tau_a[pi[u]] = va[u];
+            tau_b[pi[u]] = vb[u];
           }
         }
       }
@@ -244,7 +239,9 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
     }
     __syncthreads();  // staged state (first step) or committed state visible; counters cleared
 
-    // 2. list the agents of the request window; clear their cells' requests
+    // 2. list the agents of the request window that have an empty cell next
+    //    to them on one of their five rays (the others make no request);
+    //    clear every cell's request
     for (int i0 = threadIdx.x - lane; i0 < rw * rh; i0 += nthreads) {
       const int i = i0 + lane;
       bool agent = false;
@@ -252,8 +249,13 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
       if (i < rw * rh) {
         const int r = fast_div(i, mrw) + rlo, c = i - fast_div(i, mrw) * rw + rlo;
         ri = r * RW + c;
-        const int g = code[(r + hc - hr) * CW + c + hc - hr];
-        agent = g == kGroupA || g == kGroupB;
+        const int at = (r + hc - hr) * CW + c + hc - hr;
+        const int g = code[at];
+        if (g == kGroupA || g == kGroupB) {
+          const int d = g == kGroupA ? 1 : -1;
+          agent = code[at + d] == kEmpty || code[at - CW + d] == kEmpty || code[at + CW + d] == kEmpty ||
+                  code[at - CW] == kEmpty || code[at + CW] == kEmpty;
+        }
         rq[ri] = 0u;
       }
       const uint64_t bal = __ballot(agent);
@@ -276,14 +278,10 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
       const int at = cy * CW + cx;
       const int g = code[at];
       const int d = g == kGroupA ? 1 : -1;
-      // the cell next to the agent on each ray first: an agent with all five
-      // blocked (most of a jam) makes no request
+      // (listed agents have at least one ray open)
       uint32_t first[5];
 #pragma unroll
       for (int ray = 0; ray < 5; ++ray) first[ray] = code[at + ray_dy(ray) * CW + ray_dx(ray, d)];
-      if (first[0] != kEmpty && first[1] != kEmpty && first[2] != kEmpty && first[3] != kEmpty &&
-          first[4] != kEmpty)
-        continue;
       int f[5], d2[5];
       bool side = false;
 #pragma unroll
