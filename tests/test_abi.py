@@ -131,3 +131,28 @@ def test_tour_calls_reject_null_handle():
     assert L.sim_set_neighbours(None, 8) == pedsim.SIM_EINVAL
     assert L.sim_batch_set_neighbours(None, 8) == pedsim.SIM_EINVAL
     assert L.sim_batch_attach_tour(None, 0, None, None, None) == pedsim.SIM_EINVAL
+
+
+def test_range_calls_reject_null_handle():
+    L = pedsim.lib()
+    out = (ctypes.c_int32 * 4)()
+    assert L.sim_set_ranges(None, 3, 2) == pedsim.SIM_EINVAL
+    assert L.sim_set_range_tiling(None, 64, 32, 2, 512) == pedsim.SIM_EINVAL
+    assert L.sim_get_range_tiling(None, out) == pedsim.SIM_EINVAL
+
+
+def test_noalloc_rejects_bad_arguments_on_host():
+    """Refused before any device work: bad parameters, missing planes, an
+    unknown or tour mode, negative steps, ACO without pheromone, and a grid
+    whose scratch exceeds the static array."""
+    L = pedsim.lib()
+    st = pedsim.SimStats()
+    good = _params()
+    bad = _params(W=0)
+    assert L.sim_run_noalloc(ctypes.byref(bad), 0, 16, 16, None, 1, None, ctypes.byref(st)) == pedsim.SIM_EINVAL
+    assert L.sim_run_noalloc(ctypes.byref(good), 0, None, 16, None, 1, None, ctypes.byref(st)) == pedsim.SIM_EINVAL
+    assert L.sim_run_noalloc(ctypes.byref(good), 2, 16, 16, 16, 1, None, ctypes.byref(st)) == pedsim.SIM_EINVAL
+    assert L.sim_run_noalloc(ctypes.byref(good), 0, 16, 16, None, -1, None, ctypes.byref(st)) == pedsim.SIM_EINVAL
+    assert L.sim_run_noalloc(ctypes.byref(good), 1, 16, 16, None, 1, None, ctypes.byref(st)) == pedsim.SIM_ENOTAU
+    big = _params(W=4096, H=2048, cross_a=4, cross_b=4)
+    assert L.sim_run_noalloc(ctypes.byref(big), 0, 16, 16, None, 1, None, ctypes.byref(st)) == pedsim.SIM_ESCRATCH
