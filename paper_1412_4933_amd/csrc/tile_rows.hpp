@@ -283,7 +283,15 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
   for (int q = 0; q < 8; ++q) rq[q] = 0ull;
   uint64_t Wt[8];
 
-  for (int s = 0; s < steps; ++s) {
+  // A region without agents stays without agents in the interior for the
+  // whole launch (an agent moves at most one cell per step and the halo is
+  // 3 cells per step): its interior only evaporates, so the steps are skipped
+  // and the write-back applies `steps` evaporations with no deposit. Every
+  // wave reads the staged occupancy itself (no extra barrier).
+  const bool empty_region = __ballot(row_lane && ((H(0, 0, lane) | H(0, 1, lane)) != 0ull)) == 0ull;
+  const int run_steps = empty_region ? 0 : steps;
+
+  for (int s = 0; s < run_steps; ++s) {
     const uint64_t t = t0 + (uint64_t)s;
 
     // ---- 1. masks: requests that need no random word; who must draw -------
@@ -726,8 +734,8 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
     for (int j = 0; j < kWriteRows; ++j) {
       const int r = r0 + j * nwaves;
       rr[j] = r < R - h ? r : R - h - 1;  // rows past the interior repeat the last one, unused
-      ra[j] = H(steps, 0, rr[j]);
-      rb[j] = H(steps, 1, rr[j]);
+      ra[j] = H(run_steps, 0, rr[j]);
+      rb[j] = H(run_steps, 1, rr[j]);
       rw[j] = wall_m[rr[j]];
       rm[j] = moved_m[rr[j]];
       idv[j] = ids[rr[j] * 64 + c];
@@ -752,7 +760,7 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
       }
     }
     if (MODE == 1) {
-      for (int u = 1; u <= steps; ++u) {
+      for (int u = 1; u <= run_steps; ++u) {
 #pragma unroll
         for (int j = 0; j < kWriteRows; ++j) {
           hist_a[j] |= (uint32_t)((H(u, 0, rr[j]) >> c) & 1ull) << u;
@@ -761,7 +769,7 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
       }
     }
     if (MODE == 2) {  // bit u: an agent of the group entered the cell in step u
-      for (int u = 0; u < steps; ++u) {
+      for (int u = 0; u < run_steps; ++u) {
 #pragma unroll
         for (int j = 0; j < kWriteRows; ++j) {
           const uint64_t before = H(u, 0, rr[j]) | H(u, 1, rr[j]);
