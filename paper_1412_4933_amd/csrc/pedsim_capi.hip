@@ -291,6 +291,8 @@ int run_range_steps(sim_handle* h, int mode, int32_t nsteps, hipStream_t s, hipE
       P.code_out = dst.code;
       P.id_out = dst.id;
       P.tau_out = aco ? dst.tau : nullptr;
+      P.quads = P.W % 4 == 0 && (uintptr_t)P.code_in % 4 == 0 && (uintptr_t)P.id_in % 16 == 0 &&
+                (!aco || (uintptr_t)P.tau_in % 16 == 0);
       P.t = h->t;
       const bool last = done + chunk[j] == nsteps;
       if (ev) (void)hipEventRecord(ev[0], s);

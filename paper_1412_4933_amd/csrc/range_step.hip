@@ -176,9 +176,72 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
 
   // 1. stage the codes (outside the grid reads as wall), the ids and, for
   //    ACO, both pheromone planes (whose array is a sub-rectangle of the code
-  //    array): cells dealt to the threads in row-major order, kStageBatch
-  //    cells' loads in flight before their LDS stores
-  {
+  //    array). With aligned rows (P.quads) a load brings 4 cells: the aligned
+  //    quads of columns covering each array's rows are dealt to the threads,
+  //    kStageBatch quads of each array in flight before their LDS stores, and
+  //    only the cells inside an array are stored. Otherwise cells are dealt
+  //    one by one in row-major order, kStageBatch cells' loads in flight.
+  if (P.quads) {
+    const int W4 = W >> 2;
+    const size_t plane4 = ((size_t)W * H) >> 2;
+    const int cx0 = x0 - hc, cy0 = y0 - hc, px0 = x0 - hp, py0 = y0 - hp;
+    const int qc0 = cx0 >> 2, qp0 = px0 >> 2;  // floor: the origins may be negative
+    const int nqc = ((cx0 + CW - 1) >> 2) - qc0 + 1, nqp = ((px0 + PW - 1) >> 2) - qp0 + 1;
+    const int NC = CH * nqc, NP = PH * nqp;
+    const uint32_t mqc = div_magic((uint32_t)nqc), mqp = div_magic((uint32_t)nqp);
+    const uint32_t* code4 = (const uint32_t*)P.code_in;
+    const uint4* id4 = (const uint4*)P.id_in;
+    const uint4* tau4 = (const uint4*)P.tau_in;
+    for (int i0 = threadIdx.x; i0 < (NC > NP ? NC : NP); i0 += nthreads * kStageBatch) {
+      uint32_t vc[kStageBatch];
+      uint4 vi[kStageBatch], va[kStageBatch], vb[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int i = i0 + u * nthreads;
+        const int r = fast_div(i, mqc), q = qc0 + i - r * nqc;
+        const int gy = cy0 + r;
+        const bool in = i < NC && gy >= 0 && gy < H && q >= 0 && q < W4;
+        vc[u] = in ? code4[(size_t)gy * W4 + q] : 0x01010101u * (uint32_t)kWall;
+        const int pr = fast_div(i, mqp), pq = qp0 + i - pr * nqp;
+        const int py = py0 + pr;
+        const bool pin = i < NP && py >= 0 && py < H && pq >= 0 && pq < W4;
+        const size_t gi = pin ? (size_t)py * W4 + pq : 0;
+        vi[u] = pin ? id4[gi] : make_uint4(0u, 0u, 0u, 0u);
+        if (MODE != kModeLem) {
+          va[u] = pin ? tau4[gi] : make_uint4(0u, 0u, 0u, 0u);
+          vb[u] = pin ? tau4[plane4 + gi] : make_uint4(0u, 0u, 0u, 0u);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int i = i0 + u * nthreads;
+        if (i < NC) {
+          const int r = fast_div(i, mqc), c = 4 * (qc0 + i - r * nqc) - cx0;  // the quad's first column
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (c + e >= 0 && c + e < CW) code[r * CW + c + e] = (uint8_t)(vc[u] >> (8 * e));
+        }
+        if (i < NP) {
+          const int pr = fast_div(i, mqp), c = 4 * (qp0 + i - pr * nqp) - px0;
+          const uint32_t ev[4] = {vi[u].x, vi[u].y, vi[u].z, vi[u].w};
+          const uint32_t ea[4] = {va[u].x, va[u].y, va[u].z, va[u].w};
+          const uint32_t eb[4] = {vb[u].x, vb[u].y, vb[u].z, vb[u].w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            if (c + e >= 0 && c + e < PW) {
+              ids[pr * PW + c + e] = ev[e];
+              if (MODE != kModeLem) {
+                tau_a[pr * PW + c + e] = __uint_as_float(ea[e]);
+                tau_b[pr * PW + c + e] = __uint_as_float(eb[e]);
+              }
+            }
+          }
+        }
+      }
+    }
+    if (threadIdx.x < 2 * kRangeMax) eta_s[threadIdx.x] = P.eta[threadIdx.x / kRangeMax][threadIdx.x % kRangeMax];
+    if (threadIdx.x < 8) cnt[threadIdx.x] = 0u;
+  } else {
     const int off = hc - hp;  // the pheromone array's origin in code-array coordinates
     const size_t plane = (size_t)W * H;
     const uint32_t mc = div_magic((uint32_t)CW);

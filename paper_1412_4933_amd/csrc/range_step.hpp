@@ -31,6 +31,7 @@ struct RangeScenario {
   int alpha;
   int cross_a, cross_b;
   float eta[2][kRangeMax];  // eta^beta of a side ray: [0 lateral, 1 diagonal][free run - 1]
+  int quads;  // W % 4 == 0, codes 4-byte and ids / pheromone 16-byte aligned: stage 4 cells per load
 };
 
 // LDS of one workgroup for k steps per launch (R1 = 2M + S, the reach of one
