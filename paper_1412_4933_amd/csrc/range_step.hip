@@ -128,6 +128,7 @@ __device__ __forceinline__ int range_aco(const int f[5], const int d2[5], const 
 
 constexpr unsigned long long kNoClaim = ~0ull;
 constexpr int kStageBatch = 4;  // cells whose global loads a thread keeps in flight while staging
+constexpr int kCellBatch = 4;   // cells a thread takes at a time in the list and commit phases
 
 // q = i / d for i * d < 2^32, with m = ceil(2^32 / d): one multiply-high.
 __device__ __forceinline__ uint32_t div_magic(uint32_t d) {
@@ -304,29 +305,49 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
 
     // 2. list the agents of the request window that have an empty cell next
     //    to them on one of their five rays (the others make no request);
-    //    clear every cell's request
-    for (int i0 = threadIdx.x - lane; i0 < rw * rh; i0 += nthreads) {
-      const int i = i0 + lane;
-      bool agent = false;
-      int ri = 0;
-      if (i < rw * rh) {
-        const int r = fast_div(i, mrw) + rlo, c = i - fast_div(i, mrw) * rw + rlo;
-        ri = r * RW + c;
-        const int at = (r + hc - hr) * CW + c + hc - hr;
-        const int g = code[at];
-        if (g == kGroupA || g == kGroupB) {
-          const int d = g == kGroupA ? 1 : -1;
-          agent = code[at + d] == kEmpty || code[at - CW + d] == kEmpty || code[at + CW + d] == kEmpty ||
-                  code[at - CW] == kEmpty || code[at + CW] == kEmpty;
-        }
-        rq[ri] = 0u;
+    //    clear every cell's request. A wave takes kCellBatch runs of 64 cells
+    //    at a time, their LDS reads in flight together, and reserves the
+    //    list entries of all of them with one LDS atomic.
+    for (int i0 = threadIdx.x - lane; i0 < rw * rh; i0 += nthreads * kCellBatch) {
+      int ri[kCellBatch], at[kCellBatch], g[kCellBatch];
+      bool valid[kCellBatch], agent[kCellBatch];
+#pragma unroll
+      for (int u = 0; u < kCellBatch; ++u) {
+        const int i = i0 + u * nthreads + lane;
+        valid[u] = i < rw * rh;
+        const int ii = valid[u] ? i : 0;
+        const int r = fast_div(ii, mrw) + rlo, c = ii - fast_div(ii, mrw) * rw + rlo;
+        ri[u] = r * RW + c;
+        at[u] = (r + hc - hr) * CW + c + hc - hr;
+        g[u] = code[at[u]];
       }
-      const uint64_t bal = __ballot(agent);
-      if (bal) {
+#pragma unroll
+      for (int u = 0; u < kCellBatch; ++u) {
+        // the window lies 2 cells or more inside the code array: every
+        // neighbour read is in range, agent or not
+        const int d = g[u] == kGroupB ? -1 : 1;
+        const bool open = (code[at[u] + d] == kEmpty) | (code[at[u] - CW + d] == kEmpty) |
+                          (code[at[u] + CW + d] == kEmpty) | (code[at[u] - CW] == kEmpty) |
+                          (code[at[u] + CW] == kEmpty);
+        agent[u] = valid[u] && (g[u] == kGroupA || g[u] == kGroupB) && open;
+        if (valid[u]) rq[ri[u]] = 0u;
+      }
+      uint64_t bal[kCellBatch];
+      uint32_t total = 0u;
+#pragma unroll
+      for (int u = 0; u < kCellBatch; ++u) {
+        bal[u] = __ballot(agent[u]);
+        total += (uint32_t)__popcll(bal[u]);
+      }
+      if (total) {
         uint32_t base = 0u;
-        if (lane == 0) base = atomicAdd(&cnt[5], (uint32_t)__popcll(bal));
+        if (lane == 0) base = atomicAdd(&cnt[5], total);
         base = __shfl(base, 0);
-        if (agent) list[base + lanes_below_range(bal)] = (uint16_t)ri;
+#pragma unroll
+        for (int u = 0; u < kCellBatch; ++u) {
+          if (agent[u]) list[base + lanes_below_range(bal[u])] = (uint16_t)ri[u];
+          base += (uint32_t)__popcll(bal[u]);
+        }
       }
     }
     __syncthreads();
@@ -437,63 +458,91 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
     const int ew = TX + 2 * grow, eh = TY + 2 * grow;
     const uint32_t mew = div_magic((uint32_t)ew);
     const size_t plane = (size_t)W * H;
-    for (int i = threadIdx.x; i < ew * eh; i += nthreads) {
-      const int er = fast_div(i, mew), ec = i - er * ew;
-      const int ix = ec - grow, iy = er - grow;  // interior coordinates
-      const int gx = x0 + ix, gy = y0 + iy;
-      if (final_step && (gx >= W || gy >= H)) continue;
-      const int ci = (iy + hc) * CW + ix + hc;
-      const int pi = (iy + hp) * PW + ix + hp;
-      const int g0 = code[ci];
-      int nc = g0;
-      uint32_t nid = 0u;
-      if (g0 == kEmpty) {
-        const unsigned long long key = keys[(iy + hk) * KW + ix + hk];
-        if (key != kNoClaim) {
-          nc = (int)(key & 1ull) + 1;
-          nid = (uint32_t)((key >> 1) & 0x7fffffffull) + 1u;
-          moved += final_step ? 1u : 0u;
+    // kCellBatch cells per thread at a time: first every cell's own LDS
+    // values, then the landing cells' keys of its movers, then the stores
+    for (int i0 = threadIdx.x; i0 < ew * eh; i0 += nthreads * kCellBatch) {
+      int ix[kCellBatch], iy[kCellBatch], g0[kCellBatch], req[kCellBatch], kl[kCellBatch];
+      bool valid[kCellBatch];
+      uint32_t id0[kCellBatch];
+      unsigned long long kown[kCellBatch], kmv[kCellBatch];
+      float ta[kCellBatch], tb[kCellBatch];
+#pragma unroll
+      for (int u = 0; u < kCellBatch; ++u) {
+        const int i = i0 + u * nthreads;
+        const int ii = i < ew * eh ? i : 0;
+        const int er = fast_div(ii, mew), ec = ii - er * ew;
+        ix[u] = ec - grow;  // interior coordinates
+        iy[u] = er - grow;
+        valid[u] = i < ew * eh && !(final_step && (x0 + ix[u] >= W || y0 + iy[u] >= H));
+        const int pi = (iy[u] + hp) * PW + ix[u] + hp;
+        g0[u] = code[(iy[u] + hc) * CW + ix[u] + hc];
+        kown[u] = keys[(iy[u] + hk) * KW + ix[u] + hk];
+        id0[u] = ids[pi];
+        req[u] = rq[(iy[u] + hr) * RW + ix[u] + hr];
+        if (MODE != kModeLem) {
+          ta[u] = tau_a[pi];
+          tb[u] = tau_b[pi];
         }
-      } else if (g0 == kGroupA || g0 == kGroupB) {
-        nid = ids[pi];
-        const int code_req = rq[(iy + hr) * RW + ix + hr];
-        if (code_req) {
-          const int ray = (code_req & 7) - 1, len = code_req >> 3;
-          const int d = g0 == kGroupA ? 1 : -1;
-          const unsigned long long key =
-              keys[(iy + hk + len * ray_dy(ray)) * KW + ix + hk + len * ray_dx(ray, d)];
-          if ((uint32_t)((key >> 1) & 0x7fffffffull) == nid - 1u) {
+      }
+#pragma unroll
+      for (int u = 0; u < kCellBatch; ++u) {
+        kl[u] = -1;
+        if ((g0[u] == kGroupA || g0[u] == kGroupB) && req[u]) {
+          const int ray = (req[u] & 7) - 1, len = req[u] >> 3;
+          const int d = g0[u] == kGroupA ? 1 : -1;
+          kl[u] = (iy[u] + hk + len * ray_dy(ray)) * KW + ix[u] + hk + len * ray_dx(ray, d);
+        }
+        kmv[u] = kl[u] >= 0 ? keys[kl[u]] : kNoClaim;
+      }
+#pragma unroll
+      for (int u = 0; u < kCellBatch; ++u) {
+        if (!valid[u]) continue;
+        const int g = g0[u];
+        int nc = g;
+        uint32_t nid = 0u;
+        if (g == kEmpty) {
+          if (kown[u] != kNoClaim) {
+            nc = (int)(kown[u] & 1ull) + 1;
+            nid = (uint32_t)((kown[u] >> 1) & 0x7fffffffull) + 1u;
+            moved += final_step ? 1u : 0u;
+          }
+        } else if (g == kGroupA || g == kGroupB) {
+          nid = id0[u];
+          if (kl[u] >= 0 && (uint32_t)((kmv[u] >> 1) & 0x7fffffffull) == nid - 1u) {
             nc = kEmpty;
             nid = 0u;
           }
         }
-      }
-      float va = 0.0f, vb = 0.0f;
-      if (MODE != kModeLem) {
-        va = P.keep * tau_a[pi];
-        vb = P.keep * tau_b[pi];
-        if (nc == kGroupA) va = va + P.dtau;
-        if (nc == kGroupB) vb = vb + P.dtau;
-      }
-      if (!final_step) {
-        code[ci] = (uint8_t)nc;
-        ids[pi] = nid;
+        float va = 0.0f, vb = 0.0f;
         if (MODE != kModeLem) {
-          tau_a[pi] = va;
-          tau_b[pi] = vb;
+          va = P.keep * ta[u];
+          vb = P.keep * tb[u];
+          if (nc == kGroupA) va = va + P.dtau;
+          if (nc == kGroupB) vb = vb + P.dtau;
         }
-      } else {
-        const size_t gi = (size_t)gy * W + gx;
-        P.code_out[gi] = (uint8_t)nc;
-        P.id_out[gi] = nid;
-        if (MODE != kModeLem) {
-          P.tau_out[gi] = va;
-          P.tau_out[plane + gi] = vb;
+        const int ci = (iy[u] + hc) * CW + ix[u] + hc;
+        const int pi = (iy[u] + hp) * PW + ix[u] + hp;
+        if (!final_step) {
+          code[ci] = (uint8_t)nc;
+          ids[pi] = nid;
+          if (MODE != kModeLem) {
+            tau_a[pi] = va;
+            tau_b[pi] = vb;
+          }
+        } else {
+          const int gx = x0 + ix[u], gy = y0 + iy[u];
+          const size_t gi = (size_t)gy * W + gx;
+          P.code_out[gi] = (uint8_t)nc;
+          P.id_out[gi] = nid;
+          if (MODE != kModeLem) {
+            P.tau_out[gi] = va;
+            P.tau_out[plane + gi] = vb;
+          }
+          n_a += nc == kGroupA;
+          n_b += nc == kGroupB;
+          c_a += nc == kGroupA && gx >= W - P.cross_b;
+          c_b += nc == kGroupB && gx < P.cross_a;
         }
-        n_a += nc == kGroupA;
-        n_b += nc == kGroupB;
-        c_a += nc == kGroupA && gx >= W - P.cross_b;
-        c_b += nc == kGroupB && gx < P.cross_a;
       }
     }
     if (threadIdx.x == 0) cnt[5] = 0u;  // the next step's list (read by everyone before the last barrier)
