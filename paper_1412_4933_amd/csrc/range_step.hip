@@ -175,139 +175,43 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
   const int lane = threadIdx.x & 63;
   const int nthreads = blockDim.x;
 
-  // 1. stage the codes (outside the grid reads as wall), the ids and, for
-  //    ACO, both pheromone planes (whose array is a sub-rectangle of the code
-  //    array). With aligned rows (P.quads) a load brings 4 cells: the aligned
-  //    quads of columns covering each array's rows are dealt to the threads,
-  //    kStageBatch quads of each array in flight before their LDS stores, and
-  //    only the cells inside an array are stored. Otherwise cells are dealt
-  //    one by one in row-major order, kStageBatch cells' loads in flight.
-  if (P.quads) {
-    const int W4 = W >> 2;
-    const size_t plane4 = ((size_t)W * H) >> 2;
-    const int cx0 = x0 - hc, cy0 = y0 - hc, px0 = x0 - hp, py0 = y0 - hp;
-    const int qc0 = cx0 >> 2, qp0 = px0 >> 2;  // floor: the origins may be negative
-    const int nqc = ((cx0 + CW - 1) >> 2) - qc0 + 1, nqp = ((px0 + PW - 1) >> 2) - qp0 + 1;
-    const int NC = CH * nqc, NP = PH * nqp;
-    const uint32_t mqc = div_magic((uint32_t)nqc), mqp = div_magic((uint32_t)nqp);
-    const uint32_t* code4 = (const uint32_t*)P.code_in;
-    const uint4* id4 = (const uint4*)P.id_in;
-    const uint4* tau4 = (const uint4*)P.tau_in;
-    for (int i0 = threadIdx.x; i0 < (NC > NP ? NC : NP); i0 += nthreads * kStageBatch) {
-      uint32_t vc[kStageBatch];
-      uint4 vi[kStageBatch], va[kStageBatch], vb[kStageBatch];
-#pragma unroll
-      for (int u = 0; u < kStageBatch; ++u) {
-        const int i = i0 + u * nthreads;
-        const int r = fast_div(i, mqc), q = qc0 + i - r * nqc;
-        const int gy = cy0 + r;
-        const bool in = i < NC && gy >= 0 && gy < H && q >= 0 && q < W4;
-        vc[u] = in ? code4[(size_t)gy * W4 + q] : 0x01010101u * (uint32_t)kWall;
-        const int pr = fast_div(i, mqp), pq = qp0 + i - pr * nqp;
-        const int py = py0 + pr;
-        const bool pin = i < NP && py >= 0 && py < H && pq >= 0 && pq < W4;
-        const size_t gi = pin ? (size_t)py * W4 + pq : 0;
-        vi[u] = pin ? id4[gi] : make_uint4(0u, 0u, 0u, 0u);
-        if (MODE != kModeLem) {
-          va[u] = pin ? tau4[gi] : make_uint4(0u, 0u, 0u, 0u);
-          vb[u] = pin ? tau4[plane4 + gi] : make_uint4(0u, 0u, 0u, 0u);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kStageBatch; ++u) {
-        const int i = i0 + u * nthreads;
-        if (i < NC) {
-          const int r = fast_div(i, mqc), c = 4 * (qc0 + i - r * nqc) - cx0;  // the quad's first column
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (c + e >= 0 && c + e < CW) code[r * CW + c + e] = (uint8_t)(vc[u] >> (8 * e));
-        }
-        if (i < NP) {
-          const int pr = fast_div(i, mqp), c = 4 * (qp0 + i - pr * nqp) - px0;
-          const uint32_t ev[4] = {vi[u].x, vi[u].y, vi[u].z, vi[u].w};
-          const uint32_t ea[4] = {va[u].x, va[u].y, va[u].z, va[u].w};
-          const uint32_t eb[4] = {vb[u].x, vb[u].y, vb[u].z, vb[u].w};
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            if (c + e >= 0 && c + e < PW) {
-              ids[pr * PW + c + e] = ev[e];
-              if (MODE != kModeLem) {
-                tau_a[pr * PW + c + e] = __uint_as_float(ea[e]);
-                tau_b[pr * PW + c + e] = __uint_as_float(eb[e]);
-              }
-            }
-          }
-        }
-      }
-    }
-    if (threadIdx.x < 2 * kRangeMax) eta_s[threadIdx.x] = P.eta[threadIdx.x / kRangeMax][threadIdx.x % kRangeMax];
-    if (threadIdx.x < 8) cnt[threadIdx.x] = 0u;
-  } else {
-    const int off = hc - hp;  // the pheromone array's origin in code-array coordinates
-    const size_t plane = (size_t)W * H;
-    const uint32_t mc = div_magic((uint32_t)CW);
-    for (int i0 = threadIdx.x; i0 < CW * CH; i0 += nthreads * kStageBatch) {
-      uint32_t vc[kStageBatch], vi[kStageBatch];
-      float va[kStageBatch], vb[kStageBatch];
-      int pi[kStageBatch];
-#pragma unroll
-      for (int u = 0; u < kStageBatch; ++u) {
-        const int i = i0 + u * nthreads;
-        const int r = fast_div(i, mc), c = i - r * CW;
-        const int gx = x0 - hc + c, gy = y0 - hc + r;
-        const bool in = i < CW * CH && gx >= 0 && gx < W && gy >= 0 && gy < H;
-        const int pr = r - off, pc = c - off;
-        const bool pin = pr >= 0 && pr < PH && pc >= 0 && pc < PW;  // (i < CW * CH follows)
-        pi[u] = pin ? pr * PW + pc : -1;
-        const size_t gi = in ? (size_t)gy * W + gx : 0;
-        vc[u] = in ? P.code_in[gi] : (uint32_t)kWall;
-        vi[u] = in && pin ? P.id_in[gi] : 0u;
-        if (MODE != kModeLem) {
-          va[u] = in && pin ? P.tau_in[gi] : 0.0f;
-          vb[u] = in && pin ? P.tau_in[plane + gi] : 0.0f;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kStageBatch; ++u) {
-        const int i = i0 + u * nthreads;
-        if (i < CW * CH) code[i] = (uint8_t)vc[u];
-        if (pi[u] >= 0) {
-          ids[pi[u]] = vi[u];
-          if (MODE != kModeLem) {
-            tau_a[pi[u]] = va[u];
-            tau_b[pi[u]] = vb[u];
-          }
-        }
-      }
-    }
-    if (threadIdx.x < 2 * kRangeMax) eta_s[threadIdx.x] = P.eta[threadIdx.x / kRangeMax][threadIdx.x % kRangeMax];
-    if (threadIdx.x < 8) cnt[threadIdx.x] = 0u;
-  }
+  // this step's windows, as [lo, lo + width) in each array's coordinates:
+  // step j leaves the state exact on the interior grown by (steps - 1 - j) R1
+  auto req_window = [&](int j, int& lo, int& w, int& h) {
+    const int grow = (steps - 1 - j) * R1;
+    lo = hr - (grow + 2 * M);
+    w = TX + 2 * (grow + 2 * M);
+    h = TY + 2 * (grow + 2 * M);
+  };
+  auto key_window = [&](int j, int& lo, int& w, int& h) {
+    const int grow = (steps - 1 - j) * R1;
+    lo = hk - (grow + M);
+    w = TX + 2 * (grow + M);
+    h = TY + 2 * (grow + M);
+  };
 
-  uint32_t n_a = 0, n_b = 0, c_a = 0, c_b = 0, moved = 0;
-  for (int j = 0; j < steps; ++j) {
-    const uint64_t t = P.t + (uint64_t)j;
-    const int grow = (steps - 1 - j) * R1;  // the state after this step is needed on the interior grown by it
-    // this step's windows, as [lo, lo + width) in each array's coordinates
-    const int rlo = hr - (grow + 2 * M), rw = TX + 2 * (grow + 2 * M), rh = TY + 2 * (grow + 2 * M);
-    const int klo = hk - (grow + M), kw = TX + 2 * (grow + M), kh = TY + 2 * (grow + M);
-    const uint32_t mrw = div_magic((uint32_t)rw), mkw = div_magic((uint32_t)kw);
-
-    // clear the claims of this step's key window (the previous step's commit
-    // has passed its barrier)
+  // clear the claims of step j's key window
+  auto clear_claims = [&](int j) {
+    int klo, kw, kh;
+    key_window(j, klo, kw, kh);
+    const uint32_t mkw = div_magic((uint32_t)kw);
     for (int i = threadIdx.x; i < kw * kh; i += nthreads) {
       const int r = fast_div(i, mkw), c = i - r * kw;
       const int ki = (r + klo) * KW + c + klo;
       keys[ki] = kNoClaim;
       claims[ki] = 0u;
     }
-    __syncthreads();  // staged state (first step) or committed state visible; counters cleared
+  };
 
-    // 2. list the agents of the request window that have an empty cell next
-    //    to them on one of their five rays (the others make no request);
-    //    clear every cell's request. A wave takes kCellBatch runs of 64 cells
-    //    at a time, their LDS reads in flight together, and reserves the
-    //    list entries of all of them with one LDS atomic.
+  // 2. list the agents of step j's request window that have an empty cell
+  //    next to them on one of their five rays (the others make no request);
+  //    clear every cell's request. A wave takes kCellBatch runs of 64 cells
+  //    at a time, their LDS reads in flight together, and reserves the list
+  //    entries of all of them with one LDS atomic. Reads the codes only.
+  auto list_agents = [&](int j) {
+    int rlo, rw, rh;
+    req_window(j, rlo, rw, rh);
+    const uint32_t mrw = div_magic((uint32_t)rw);
     for (int i0 = threadIdx.x - lane; i0 < rw * rh; i0 += nthreads * kCellBatch) {
       int ri[kCellBatch], at[kCellBatch], g[kCellBatch];
       bool valid[kCellBatch], agent[kCellBatch];
@@ -350,7 +254,153 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
         }
       }
     }
-    __syncthreads();
+  };
+
+  // 1. stage the codes (outside the grid reads as wall), the ids and, for
+  //    ACO, both pheromone planes (whose array is a sub-rectangle of the code
+  //    array). With aligned rows (P.quads) a load brings 4 cells: the aligned
+  //    quads of columns covering each array's rows are dealt to the threads,
+  //    kStageBatch quads of each array in flight before their LDS stores, and
+  //    only the cells inside an array are stored. The first step's list reads
+  //    only the codes, so the ids and pheromone of a thread's first batch stay
+  //    in its registers, their loads in flight, until that list is built.
+  //    Without aligned rows cells are dealt one by one in row-major order,
+  //    kStageBatch cells' loads in flight.
+  const int W4 = W >> 2;
+  const size_t plane4 = ((size_t)W * H) >> 2;
+  const int cx0 = x0 - hc, cy0 = y0 - hc, px0 = x0 - hp, py0 = y0 - hp;
+  const int qc0 = cx0 >> 2, qp0 = px0 >> 2;  // floor: the origins may be negative
+  const int nqc = ((cx0 + CW - 1) >> 2) - qc0 + 1, nqp = ((px0 + PW - 1) >> 2) - qp0 + 1;
+  const int NC = CH * nqc, NP = PH * nqp;
+  const uint32_t mqc = div_magic((uint32_t)nqc), mqp = div_magic((uint32_t)nqp);
+  const uint32_t* code4 = (const uint32_t*)P.code_in;
+  const uint4* id4 = (const uint4*)P.id_in;
+  const uint4* tau4 = (const uint4*)P.tau_in;
+  auto load_code_quad = [&](int i) -> uint32_t {
+    const int r = fast_div(i, mqc), q = qc0 + i - r * nqc;
+    const int gy = cy0 + r;
+    const bool in = i < NC && gy >= 0 && gy < H && q >= 0 && q < W4;
+    return in ? code4[(size_t)gy * W4 + q] : 0x01010101u * (uint32_t)kWall;
+  };
+  auto store_code_quad = [&](int i, uint32_t v) {
+    if (i >= NC) return;
+    const int r = fast_div(i, mqc), c = 4 * (qc0 + i - r * nqc) - cx0;  // the quad's first column
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (c + e >= 0 && c + e < CW) code[r * CW + c + e] = (uint8_t)(v >> (8 * e));
+  };
+  // the id, pheromone A and pheromone B quads of p-array quad i
+  auto load_p_quad = [&](int i, uint4& vi, uint4& va, uint4& vb) {
+    const int pr = fast_div(i, mqp), pq = qp0 + i - pr * nqp;
+    const int py = py0 + pr;
+    const bool pin = i < NP && py >= 0 && py < H && pq >= 0 && pq < W4;
+    const size_t gi = pin ? (size_t)py * W4 + pq : 0;
+    // (a zero written as a value: a captured constant would turn the select
+    // into a generic-address load)
+    vi = pin ? id4[gi] : make_uint4(0u, 0u, 0u, 0u);
+    if (MODE != kModeLem) {
+      va = pin ? tau4[gi] : make_uint4(0u, 0u, 0u, 0u);
+      vb = pin ? tau4[plane4 + gi] : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto store_p_quad = [&](int i, const uint4& vi, const uint4& va, const uint4& vb) {
+    if (i >= NP) return;
+    const int pr = fast_div(i, mqp), c = 4 * (qp0 + i - pr * nqp) - px0;
+    const uint32_t ev[4] = {vi.x, vi.y, vi.z, vi.w};
+    const uint32_t ea[4] = {va.x, va.y, va.z, va.w};
+    const uint32_t eb[4] = {vb.x, vb.y, vb.z, vb.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (c + e >= 0 && c + e < PW) {
+        ids[pr * PW + c + e] = ev[e];
+        if (MODE != kModeLem) {
+          tau_a[pr * PW + c + e] = __uint_as_float(ea[e]);
+          tau_b[pr * PW + c + e] = __uint_as_float(eb[e]);
+        }
+      }
+    }
+  };
+  uint4 held_i[kStageBatch], held_a[kStageBatch], held_b[kStageBatch];
+  if (P.quads) {
+    // the first batch's codes are stored before its other loads are issued:
+    // a wait for a load also waits for every load issued before it
+    uint32_t vc[kStageBatch];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) vc[u] = load_code_quad(threadIdx.x + u * nthreads);
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) store_code_quad(threadIdx.x + u * nthreads, vc[u]);
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) load_p_quad(threadIdx.x + u * nthreads, held_i[u], held_a[u], held_b[u]);
+    // later batches (regions larger than one batch per thread) go straight to LDS
+    for (int i0 = threadIdx.x + nthreads * kStageBatch; i0 < (NC > NP ? NC : NP); i0 += nthreads * kStageBatch) {
+      uint4 vi[kStageBatch], va[kStageBatch], vb[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        load_p_quad(i0 + u * nthreads, vi[u], va[u], vb[u]);
+        vc[u] = load_code_quad(i0 + u * nthreads);
+      }
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        store_code_quad(i0 + u * nthreads, vc[u]);
+        store_p_quad(i0 + u * nthreads, vi[u], va[u], vb[u]);
+      }
+    }
+  } else {
+    const int off = hc - hp;  // the pheromone array's origin in code-array coordinates
+    const size_t plane = (size_t)W * H;
+    const uint32_t mc = div_magic((uint32_t)CW);
+    for (int i0 = threadIdx.x; i0 < CW * CH; i0 += nthreads * kStageBatch) {
+      uint32_t vc[kStageBatch], vi[kStageBatch];
+      float va[kStageBatch], vb[kStageBatch];
+      int pi[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int i = i0 + u * nthreads;
+        const int r = fast_div(i, mc), c = i - r * CW;
+        const int gx = x0 - hc + c, gy = y0 - hc + r;
+        const bool in = i < CW * CH && gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const int pr = r - off, pc = c - off;
+        const bool pin = pr >= 0 && pr < PH && pc >= 0 && pc < PW;  // (i < CW * CH follows)
+        pi[u] = pin ? pr * PW + pc : -1;
+        const size_t gi = in ? (size_t)gy * W + gx : 0;
+        vc[u] = in ? P.code_in[gi] : (uint32_t)kWall;
+        vi[u] = in && pin ? P.id_in[gi] : 0u;
+        if (MODE != kModeLem) {
+          va[u] = in && pin ? P.tau_in[gi] : 0.0f;
+          vb[u] = in && pin ? P.tau_in[plane + gi] : 0.0f;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int i = i0 + u * nthreads;
+        if (i < CW * CH) code[i] = (uint8_t)vc[u];
+        if (pi[u] >= 0) {
+          ids[pi[u]] = vi[u];
+          if (MODE != kModeLem) {
+            tau_a[pi[u]] = va[u];
+            tau_b[pi[u]] = vb[u];
+          }
+        }
+      }
+    }
+  }
+  if (threadIdx.x < 2 * kRangeMax) eta_s[threadIdx.x] = P.eta[threadIdx.x / kRangeMax][threadIdx.x % kRangeMax];
+  if (threadIdx.x < 8) cnt[threadIdx.x] = 0u;
+  clear_claims(0);
+  __syncthreads();  // codes staged, counters and the first step's claims cleared
+  list_agents(0);
+  if (P.quads) {
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) store_p_quad(threadIdx.x + u * nthreads, held_i[u], held_a[u], held_b[u]);
+  }
+  __syncthreads();  // ids, pheromone and the first step's list in place
+
+  uint32_t n_a = 0, n_b = 0, c_a = 0, c_b = 0, moved = 0;
+  for (int j = 0; j < steps; ++j) {
+    const uint64_t t = P.t + (uint64_t)j;
+    const int grow = (steps - 1 - j) * R1;  // the state after this step is needed on the interior grown by it
+    int klo, kw, kh;
+    key_window(j, klo, kw, kh);
     const int n_agents = (int)cnt[5];
 
     // 3. requests of the listed agents; every landing cell counts its claims
@@ -545,8 +595,13 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
         }
       }
     }
-    if (threadIdx.x == 0) cnt[5] = 0u;  // the next step's list (read by everyone before the last barrier)
-    if (!final_step) __syncthreads();  // the commit's key reads and LDS writes before the next step
+    if (threadIdx.x == 0) cnt[5] = 0u;  // the next step's list (read by everyone before the resolve barrier)
+    if (!final_step) {
+      __syncthreads();  // the commit's key reads and LDS writes before the next step's clear and list
+      clear_claims(j + 1);
+      list_agents(j + 1);
+      __syncthreads();
+    }
   }
 
   if (last) {
