@@ -169,6 +169,13 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
   float* eta_s = (float*)(cnt + 8);             // eta^beta: [0 lateral, 1 diagonal][free run - 1]
   float* tau_a = (float*)(smem + L.tau());      // ACO: [PH][PW] per plane
   float* tau_b = tau_a + (size_t)PW * PH;
+  // ACO, k > 1: the pheromone arrays keep their staged values for the whole
+  // launch; a cell's value after step u is evaluated when needed from the
+  // occupancy it had after each step v <= u (2 bits per step: 0 empty or
+  // wall, 1 A, 2 B), with the operations of the per-step update in its order
+  uint8_t* hist = smem + L.hist();
+  constexpr bool kAco = MODE != kModeLem;
+  const bool lazy = kAco && steps > 1;
 
   const int x0 = (tile % P.tiles_x) * TX, y0 = (tile / P.tiles_x) * TY;
   const int W = P.W, H = P.H;
@@ -389,6 +396,16 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
   clear_claims(0);
   __syncthreads();  // codes staged, counters and the first step's claims cleared
   list_agents(0);
+  if (lazy) {  // every slot holds the staged occupancy, on the cells whose value is read later
+    const int g0w = (steps - 1) * R1;
+    const int ew = TX + 2 * g0w, eh = TY + 2 * g0w;
+    const uint32_t mew = div_magic((uint32_t)ew);
+    for (int i = threadIdx.x; i < ew * eh; i += nthreads) {
+      const int er = fast_div(i, mew), ec = i - er * ew;
+      const int g = code[(er - g0w + hc) * CW + ec - g0w + hc];
+      hist[(er - g0w + hp) * PW + ec - g0w + hp] = (uint8_t)(g == kGroupA ? 0x55u : (g == kGroupB ? 0xAAu : 0u));
+    }
+  }
   if (P.quads) {
 #pragma unroll
     for (int u = 0; u < kStageBatch; ++u) store_p_quad(threadIdx.x + u * nthreads, held_i[u], held_a[u], held_b[u]);
@@ -461,7 +478,16 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
             if (f[ray] >= 1) {
               const int k = f[ray] < M ? f[ray] : M;
               eta[ray] = eta_s[(ray <= 2 ? kRangeMax : 0) + f[ray] - 1];
-              tau[ray] = tp[(py + k * ray_dy(ray)) * PW + px + k * ray_dx(ray, d)];
+              const int li = (py + k * ray_dy(ray)) * PW + px + k * ray_dx(ray, d);
+              float x = tp[li];
+              if (lazy && j > 0) {  // the updates of steps 0 .. j-1
+                const uint32_t hc_ = hist[li];
+                for (int v = 0; v < j; ++v) {
+                  x = P.keep * x;
+                  if ((int)((hc_ >> (2 * v)) & 3u) == g) x = x + P.dtau;
+                }
+              }
+              tau[ray] = x;
             }
           }
           choice = range_aco(f, d2, tau, eta, P.alpha, w.w1, w.w2);
@@ -502,9 +528,43 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
     }
     __syncthreads();
 
-    // 5. commit on the interior grown by `grow`: in place in LDS, or (last
-    //    step) the interior to the output planes, with pheromone and counters
+    // 5. commit on the interior grown by `grow`. Before the last step, in
+    //    place in LDS and only where something moves: every listed agent that
+    //    won its landing cell leaves its cell and enters the landing cell
+    //    (each inside the window); nothing else changes but the pheromone,
+    //    which is evaluated lazily from the occupancy history. The last step
+    //    writes the interior to the output planes, with pheromone and counters.
     const bool final_step = j == steps - 1;
+    if (!final_step) {
+      const uint32_t slots = (0x3Fu << (2 * j)) & 0x3Fu;  // history slots of steps j .. k-2
+      for (int q = threadIdx.x; q < n_agents; q += nthreads) {
+        const int ri = list[q];
+        const int code_req = rq[ri];
+        if (!code_req) continue;
+        const int r = fast_div(ri, mRW), c = ri - r * RW;
+        const int ix = c - hr, iy = r - hr;  // interior coordinates of the agent's cell
+        const int ci = (iy + hc) * CW + ix + hc, pi = (iy + hp) * PW + ix + hp;
+        const int g = code[ci];
+        const int ray = (code_req & 7) - 1, len = code_req >> 3;
+        const int d = g == kGroupA ? 1 : -1;
+        const int tx_ = ix + len * ray_dx(ray, d), ty_ = iy + len * ray_dy(ray);
+        if (tx_ + hk < klo || tx_ + hk >= klo + kw || ty_ + hk < klo || ty_ + hk >= klo + kh) continue;
+        const uint32_t nid = ids[pi];
+        const unsigned long long key = keys[(ty_ + hk) * KW + tx_ + hk];
+        if ((uint32_t)((key >> 1) & 0x7fffffffull) != nid - 1u) continue;  // lost its contest
+        if (ix >= -grow && ix < TX + grow && iy >= -grow && iy < TY + grow) {
+          code[ci] = (uint8_t)kEmpty;
+          ids[pi] = 0u;
+          if (lazy) hist[pi] = (uint8_t)(hist[pi] & ~slots);
+        }
+        if (tx_ >= -grow && tx_ < TX + grow && ty_ >= -grow && ty_ < TY + grow) {
+          const int ti = (ty_ + hp) * PW + tx_ + hp;
+          code[(ty_ + hc) * CW + tx_ + hc] = (uint8_t)g;
+          ids[ti] = nid;
+          if (lazy) hist[ti] = (uint8_t)((hist[ti] & ~slots) | ((g == kGroupA ? 0x55u : 0xAAu) & slots));
+        }
+      }
+    } else {
     const int ew = TX + 2 * grow, eh = TY + 2 * grow;
     const uint32_t mew = div_magic((uint32_t)ew);
     const size_t plane = (size_t)W * H;
@@ -513,7 +573,7 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
     for (int i0 = threadIdx.x; i0 < ew * eh; i0 += nthreads * kCellBatch) {
       int ix[kCellBatch], iy[kCellBatch], g0[kCellBatch], req[kCellBatch], kl[kCellBatch];
       bool valid[kCellBatch];
-      uint32_t id0[kCellBatch];
+      uint32_t id0[kCellBatch], h0[kCellBatch];
       unsigned long long kown[kCellBatch], kmv[kCellBatch];
       float ta[kCellBatch], tb[kCellBatch];
 #pragma unroll
@@ -523,7 +583,7 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
         const int er = fast_div(ii, mew), ec = ii - er * ew;
         ix[u] = ec - grow;  // interior coordinates
         iy[u] = er - grow;
-        valid[u] = i < ew * eh && !(final_step && (x0 + ix[u] >= W || y0 + iy[u] >= H));
+        valid[u] = i < ew * eh && x0 + ix[u] < W && y0 + iy[u] < H;
         const int pi = (iy[u] + hp) * PW + ix[u] + hp;
         g0[u] = code[(iy[u] + hc) * CW + ix[u] + hc];
         kown[u] = keys[(iy[u] + hk) * KW + ix[u] + hk];
@@ -532,6 +592,7 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
         if (MODE != kModeLem) {
           ta[u] = tau_a[pi];
           tb[u] = tau_b[pi];
+          h0[u] = lazy ? hist[pi] : 0u;
         }
       }
 #pragma unroll
@@ -565,21 +626,23 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
         }
         float va = 0.0f, vb = 0.0f;
         if (MODE != kModeLem) {
-          va = P.keep * ta[u];
-          vb = P.keep * tb[u];
+          va = ta[u];
+          vb = tb[u];
+          if (lazy) {  // the updates of steps 0 .. k-2
+            for (int v = 0; v < steps - 1; ++v) {
+              const uint32_t o = (h0[u] >> (2 * v)) & 3u;
+              va = P.keep * va;
+              vb = P.keep * vb;
+              if (o == (uint32_t)kGroupA) va = va + P.dtau;
+              if (o == (uint32_t)kGroupB) vb = vb + P.dtau;
+            }
+          }
+          va = P.keep * va;
+          vb = P.keep * vb;
           if (nc == kGroupA) va = va + P.dtau;
           if (nc == kGroupB) vb = vb + P.dtau;
         }
-        const int ci = (iy[u] + hc) * CW + ix[u] + hc;
-        const int pi = (iy[u] + hp) * PW + ix[u] + hp;
-        if (!final_step) {
-          code[ci] = (uint8_t)nc;
-          ids[pi] = nid;
-          if (MODE != kModeLem) {
-            tau_a[pi] = va;
-            tau_b[pi] = vb;
-          }
-        } else {
+        {
           const int gx = x0 + ix[u], gy = y0 + iy[u];
           const size_t gi = (size_t)gy * W + gx;
           P.code_out[gi] = (uint8_t)nc;
@@ -594,6 +657,7 @@ __global__ __launch_bounds__(kRangeMaxThreads) void range_kernel(RangeScenario P
           c_b += nc == kGroupB && gx < P.cross_a;
         }
       }
+    }
     }
     if (threadIdx.x == 0) cnt[5] = 0u;  // the next step's list (read by everyone before the resolve barrier)
     if (!final_step) {

@@ -38,7 +38,8 @@ struct RangeScenario {
 // step): codes of the interior plus k R1 (1 B/cell); ids and, for ACO, both
 // pheromone planes of the interior plus (k-1) R1 + 3M; request bytes and the
 // compacted agent list of the interior plus (k-1) R1 + 2M; claim keys and
-// counts of the interior plus (k-1) R1 + M; counters and the heuristic table.
+// counts of the interior plus (k-1) R1 + M; counters and the heuristic table;
+// for ACO with k > 1 an occupancy history byte per pheromone cell.
 struct RangeLayout {
   int TX, TY, S, M, K;
   bool aco;
@@ -53,8 +54,11 @@ struct RangeLayout {
   __host__ __device__ size_t claims() const { return keys() + cells((K - 1) * r1() + M) * 8; }
   __host__ __device__ size_t ctl() const { return up16(claims() + cells((K - 1) * r1() + M) * 4); }
   __host__ __device__ size_t tau() const { return ctl() + 32 * 4; }  // ctl: 8 counters, 16 eta, pad
+  // ACO with k > 1: the occupancy after each of the launch's first k - 1
+  // steps, 2 bits per step, per cell of the pheromone array
+  __host__ __device__ size_t hist() const { return tau() + (aco ? (size_t)2 * cells((K - 1) * r1() + 3 * M) * 4 : 0); }
   __host__ __device__ size_t bytes() const {
-    return tau() + (aco ? (size_t)2 * cells((K - 1) * r1() + 3 * M) * 4 : 0);
+    return hist() + (aco && K > 1 ? up16(cells((K - 1) * r1() + 3 * M)) : 0);
   }
 };
 
