@@ -100,8 +100,9 @@ typedef struct {
 
 /* Bytes of device scratch a scenario with these parameters needs: a shadow
  * copy of the planes the step kernels ping-pong with (13 bytes per cell:
- * code 1, id 4, both pheromone planes 8) plus per-tile counters and a few
- * 64-bit totals. */
+ * code 1, id 4, both pheromone planes 8) plus per-tile counters, a few
+ * 64-bit totals and the order in which the row-lane launches deal out their
+ * tiles (three rotations of one word per tile; it changes no result). */
 int sim_scratch_bytes(const sim_params* p, size_t* out);
 
 /*

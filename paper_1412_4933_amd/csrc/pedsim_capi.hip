@@ -42,7 +42,8 @@ ScratchLayout layout_of(const sim_params* p) {
   L.tau2 = L.id2 + round_up(cells * 4);
   L.stats = L.tau2 + round_up(cells * 8);
   L.totals = L.stats + round_up((size_t)L.stats_cap * kTileStatFields * 4);
-  L.total = L.totals + round_up(8 * sizeof(unsigned long long));
+  L.order = L.totals + round_up(8 * sizeof(unsigned long long));
+  L.total = L.order + round_up((size_t)3 * (16 + L.stats_cap) * 4);
   return L;
 }
 
@@ -174,6 +175,15 @@ struct sim_handle {
   int scan, move;
   int range_cols, range_rows, range_steps, range_threads;
   float range_eta[2][kRangeMax];
+  // tile order of the row-lane launches (see Scenario::order): the tiling
+  // the rotations were written for, the rotation the next launch takes and
+  // whether it holds a complete order
+  uint32_t* order;
+  Tiling order_tl;
+  int order_mode;
+  int order_rot;
+  bool order_valid;
+  bool order_on;  // the tile grid has more tiles than the device runs at once
 };
 
 namespace {
@@ -338,6 +348,17 @@ int run_steps(sim_handle* h, int mode, int32_t nsteps, hipStream_t s, hipEvent_t
   const Tiling& tl = h->tiling[mode];
   Scenario S = h->base;
   set_geometry(S, tl);
+  if (rows_engine(tl) && (h->order_tl.nw != tl.nw || h->order_tl.rows != tl.rows || h->order_tl.steps != tl.steps ||
+                          h->order_tl.threads != tl.threads || h->order_mode != mode)) {
+    // another tile grid or kernel: start from row-major order
+    PEDSIM_HIP(launch_zero_words(h->order, (size_t)3 * (16 + h->stats_cap), s));
+    h->order_tl = tl;
+    h->order_mode = mode;
+    h->order_rot = 0;
+    h->order_valid = false;
+    h->order_on = rows_order_pays(S, tl, mode);
+  }
+  const bool ordered = rows_engine(tl) && h->order_on;
   const size_t cells = (size_t)S.W * (size_t)S.H;
   const bool aco = mode != kModeLem;
   const bool tour = mode == kModeAcoTour;
@@ -359,9 +380,17 @@ int run_steps(sim_handle* h, int mode, int32_t nsteps, hipStream_t s, hipEvent_t
       S.tour_in = tour ? src.tour : nullptr;
       S.tour_out = tour ? dst.tour : nullptr;
       S.tile_stats = h->stats;
+      S.order = ordered ? h->order : nullptr;
+      S.order_cap = h->stats_cap;
+      S.order_rot = h->order_rot;
+      S.order_valid = h->order_valid ? 1 : 0;
       const bool last = done + chunk[j] == nsteps;
       if (ev) (void)hipEventRecord(ev[0], s);
       PEDSIM_HIP(launch_tiles(S, tl, mode, h->t, chunk[j], last, s));
+      if (ordered) {
+        h->order_rot = (h->order_rot + 1) % 3;
+        h->order_valid = true;
+      }
       if (ev) {
         (void)hipEventRecord(ev[1], s);
         PEDSIM_HIP(hipEventSynchronize(ev[1]));
@@ -418,6 +447,10 @@ int init_handle(sim_handle* h, const sim_params* p, uint8_t* d_code, uint32_t* d
   h->scan = h->move = 0;
   h->range_cols = h->range_rows = h->range_steps = h->range_threads = 0;
   memset(h->range_eta, 0, sizeof(h->range_eta));
+  h->order = (uint32_t*)(scratch + L.order);
+  h->order_tl = Tiling{-1, 0, 0, 0};  // no order yet: the first row-lane launch clears the rotations
+  h->order_mode = -1;
+  h->order_on = false;
   PEDSIM_HIP(launch_count(d_code, p->W, p->H, p->cross_a, p->cross_b, h->stats, &h->stats_entries, s));
   PEDSIM_HIP(hipStreamSynchronize(s));
   return SIM_OK;

@@ -41,6 +41,11 @@ inline int region_cols(const Tiling& tl) { return rows_engine(tl) ? 64 : 64 * tl
 size_t tile_lds_bytes(const Tiling& tl, int mode, bool nb8 = false);
 bool tiling_valid(const Tiling& tl, int mode, int max_lds, bool nb8 = false);
 
+// Whether the row-lane launches of S with tiling tl run more workgroups than
+// the device holds at once, so that the order in which tiles are dealt out
+// matters (see Scenario::order).
+bool rows_order_pays(const Scenario& S, const Tiling& tl, int mode);
+
 // One launch of the tile engine over every tile of S.
 hipError_t launch_tiles(const Scenario& S, const Tiling& tl, int mode, uint64_t t0, int steps, int last,
                         hipStream_t s);
@@ -82,7 +87,7 @@ struct Planes {
 // Per-scenario scratch: shadow planes (code, id, both pheromone planes),
 // per-tile counters, totals and validation counters.
 struct ScratchLayout {
-  size_t code2, id2, tau2, stats, totals, total;
+  size_t code2, id2, tau2, stats, totals, order, total;
   int stats_cap;
 };
 

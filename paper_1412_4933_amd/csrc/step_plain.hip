@@ -21,15 +21,66 @@ __global__ __launch_bounds__(1024) void tile_kernel(Scenario S, int R, uint64_t 
   advance_tile<NW, MODE>(S, smem, R, tile % S.tiles_x, tile / S.tiles_x, tile, t0, steps, last != 0);
 }
 
-template <int MODE, bool STREAM, bool NB8 = false>
+// On grids with more tiles than a launch runs at once, the tiles that hold
+// agents take several times longer than the empty ones, and a busy tile
+// dealt out late extends the launch. Each XCD therefore deals its tiles in the
+// order the previous launch recorded: the tiles that had agents first. The
+// order only changes which workgroup takes which tile, never the result.
+// The tile a workgroup takes (-1: none): the XCD's run of tiles in the order
+// the previous launch recorded, or in row-major order.
+__device__ __forceinline__ int pick_tile(const Scenario& S) {
+  const int ntiles = S.tiles_x * S.tiles_y;
+  const int per = (ntiles + 7) >> 3;
+  const int x = blockIdx.x & 7, j = blockIdx.x >> 3;  // XCD, and the workgroup's place in its run
+  const int run = ntiles - x * per < per ? ntiles - x * per : per;
+  if (j >= run) return -1;
+  if (S.order) {
+    const size_t stride = 16 + (size_t)S.order_cap;
+    if (blockIdx.x == 0 && threadIdx.x < 16) S.order[(size_t)((S.order_rot + 2) % 3) * stride + threadIdx.x] = 0u;
+    if (S.order_valid) {
+      const uint32_t t = S.order[(size_t)S.order_rot * stride + 16 + x * per + j];
+      if (t < (uint32_t)ntiles) return (int)t;  // (always, when the previous launch recorded the order)
+    }
+  }
+  return x * per + j;
+}
+
+// Records `tile` in the next launch's order: from the front of its XCD's run
+// if it held agents, from the back otherwise.
+__device__ __forceinline__ void record_tile(const Scenario& S, int tile, bool busy) {
+  const int ntiles = S.tiles_x * S.tiles_y;
+  const int per = (ntiles + 7) >> 3;
+  const int x = blockIdx.x & 7;
+  const int run = ntiles - x * per < per ? ntiles - x * per : per;
+  uint32_t* wr = S.order + (size_t)((S.order_rot + 1) % 3) * (16 + (size_t)S.order_cap);
+  const uint32_t slot = atomicAdd(&wr[2 * x + (busy ? 0 : 1)], 1u);
+  if (slot < (uint32_t)run) wr[16 + x * per + (busy ? (int)slot : run - 1 - (int)slot)] = (uint32_t)tile;
+}
+
+// On grids with more tiles than the device runs at once, the tiles that hold
+// agents take several times longer than the empty ones, and a busy tile
+// dealt out late extends the launch. Each XCD therefore deals its tiles in the
+// order the previous launch recorded: the tiles that had agents first. The
+// order only changes which workgroup takes which tile, never the result.
+// ORDERED: S.order is set. Without it the kernel is the plain row-major one
+// (no order state kept live through the step phases).
+template <int MODE, bool STREAM, bool NB8 = false, bool ORDERED = false>
 __global__ __launch_bounds__(kRowsMaxThreads, kRowsMinWavesPerSimd) void tile_rows_kernel(Scenario S, int R, int k_max, uint64_t t0,
                                                                     int steps, int last) {
   extern __shared__ __align__(16) uint8_t smem[];
-  const int ntiles = S.tiles_x * S.tiles_y;
-  const int tile = tile_of_block(blockIdx.x, ntiles);
-  if (tile >= ntiles) return;
-  advance_tile_rows<MODE, STREAM, NB8>(S, smem, R, k_max, tile % S.tiles_x, tile / S.tiles_x, tile, t0, steps,
-                                       last != 0);
+  if (!ORDERED) {
+    const int ntiles = S.tiles_x * S.tiles_y;
+    const int tile = tile_of_block(blockIdx.x, ntiles);
+    if (tile >= ntiles) return;
+    advance_tile_rows<MODE, STREAM, NB8>(S, smem, R, k_max, tile % S.tiles_x, tile / S.tiles_x, tile, t0, steps,
+                                         last != 0);
+    return;
+  }
+  const int tile = pick_tile(S);
+  if (tile < 0) return;
+  const bool busy = advance_tile_rows<MODE, STREAM, NB8>(S, smem, R, k_max, tile % S.tiles_x, tile / S.tiles_x,
+                                                         tile, t0, steps, last != 0);
+  if (threadIdx.x == 0) record_tile(S, tile, busy);
 }
 
 size_t tile_lds_bytes(const Tiling& tl, int mode, bool nb8) {
@@ -78,19 +129,60 @@ static hipError_t launch_one(const Scenario& S, const Tiling& tl, uint64_t t0, i
 }
 
 template <int MODE, bool STREAM, bool NB8 = false>
-static hipError_t launch_rows(const Scenario& S, const Tiling& tl, uint64_t t0, int steps, int last, hipStream_t s) {
-  const size_t lds = RowsLayout{tl.rows, tl.steps, MODE != kModeLem, STREAM, MODE == kModeAcoTour, NB8}.bytes();
+static size_t rows_prepare(const Tiling& tl) {
   static bool attr_done = false;
   if (!attr_done) {
-    (void)hipFuncSetAttribute((const void*)tile_rows_kernel<MODE, STREAM, NB8>,
+    (void)hipFuncSetAttribute((const void*)tile_rows_kernel<MODE, STREAM, NB8, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, max_dynamic_lds());
+    (void)hipFuncSetAttribute((const void*)tile_rows_kernel<MODE, STREAM, NB8, true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, max_dynamic_lds());
     (void)hipGetLastError();  // an unsupported attribute value must not linger as the last error
     attr_done = true;
   }
+  return RowsLayout{tl.rows, tl.steps, MODE != kModeLem, STREAM, MODE == kModeAcoTour, NB8}.bytes();
+}
+
+// Workgroups of this kernel the whole device runs at once (0 if unknown).
+template <int MODE, bool STREAM, bool NB8 = false>
+static long rows_resident(const Tiling& tl) {
+  const size_t lds = rows_prepare<MODE, STREAM, NB8>(tl);
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)tile_rows_kernel<MODE, STREAM, NB8, true>,
+                                                   tl.threads, lds) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return (long)per_cu * cus;
+}
+
+template <int MODE, bool STREAM, bool NB8 = false>
+static hipError_t launch_rows(const Scenario& S, const Tiling& tl, uint64_t t0, int steps, int last, hipStream_t s) {
+  const size_t lds = rows_prepare<MODE, STREAM, NB8>(tl);
   const int ntiles = S.tiles_x * S.tiles_y;
   const int blocks = ((ntiles + 7) / 8) * 8;
-  tile_rows_kernel<MODE, STREAM, NB8><<<blocks, tl.threads, lds, s>>>(S, tl.rows, tl.steps, t0, steps, last);
+  if (S.order)
+    tile_rows_kernel<MODE, STREAM, NB8, true><<<blocks, tl.threads, lds, s>>>(S, tl.rows, tl.steps, t0, steps, last);
+  else
+    tile_rows_kernel<MODE, STREAM, NB8, false><<<blocks, tl.threads, lds, s>>>(S, tl.rows, tl.steps, t0, steps, last);
   return hipGetLastError();
+}
+
+bool rows_order_pays(const Scenario& S, const Tiling& tl, int mode) {
+  if (!rows_engine(tl)) return false;
+  long resident = 0;
+  if (S.neighbours == 8)
+    resident = mode == kModeLem ? rows_resident<kModeLem, false, true>(tl)
+                                : (mode == kModeAco ? rows_resident<kModeAco, false, true>(tl)
+                                                    : rows_resident<kModeAcoTour, false, true>(tl));
+  else if (mode == kModeAcoTour)
+    resident = rows_resident<kModeAcoTour, false>(tl);
+  else if (rows_stream(tl))
+    resident = mode == kModeLem ? rows_resident<kModeLem, true>(tl) : rows_resident<kModeAco, true>(tl);
+  else
+    resident = mode == kModeLem ? rows_resident<kModeLem, false>(tl) : rows_resident<kModeAco, false>(tl);
+  return resident > 0 && (long)S.tiles_x * S.tiles_y > resident;
 }
 
 hipError_t launch_tiles(const Scenario& S, const Tiling& tl, int mode, uint64_t t0, int steps, int last,

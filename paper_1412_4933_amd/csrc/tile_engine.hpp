@@ -92,6 +92,14 @@ struct Scenario {
   int neighbours;                 // 5 (no backward cells) or 8
   int alpha;
   int cross_a, cross_b;
+  // Row-lane launches of one scenario: the order in which each XCD's
+  // workgroups take its tiles. Three rotations of [16 counters][order_cap
+  // entries]: a launch takes rotation order_rot (if order_valid; else the
+  // tiles in row-major order), writes the next one (per XCD, the tiles that
+  // had agents from the front, the others from the back) and clears the
+  // counters of the one after. nullptr: row-major order, nothing written.
+  uint32_t* order;
+  int order_cap, order_rot, order_valid;
 };
 
 // LDS layout of a region of R rows x 64*NW columns.

@@ -177,8 +177,9 @@ __device__ __forceinline__ void stage_issue(const Scenario& S, int R, int x0, in
 // dir_dr(q)) of a cell into the cell, i.e. by the vector (-dir_dc(q),
 // -dir_dr(q)); forward moves are directions 0 (A) and 1 (B), and every
 // direction may carry either group.
+// Returns whether the region held agents at the start of the launch.
 template <int MODE, bool STREAM = false, bool NB8 = false>
-__device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k_max, int tx, int ty, int tile_index,
+__device__ bool advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k_max, int tx, int ty, int tile_index,
                                   uint64_t t0, int steps, bool last) {
   static_assert(!(NB8 && STREAM), "the eight-neighbour set runs on the LDS form only");
   // Contest tickets are kept per cell from the draw, except in the streaming
@@ -834,6 +835,7 @@ __device__ void advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
     __syncthreads();
     if (tid < kTileStatFields) S.tile_stats[(size_t)tile_index * kTileStatFields + tid] = ctl[8 + tid];
   }
+  return !empty_region;
 }
 
 }  // namespace pedsim
