@@ -10,6 +10,7 @@
 // use). Calls with more launches than one graph holds are split.
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -62,6 +63,7 @@ struct sim_batch {
   bool upload_pending;
   hipStream_t capture;  // private stream the launch sequences are captured on
   std::vector<HostSlot> slots;
+  std::vector<int> order;  // slots in the order their tiles are claimed
   Tiling tl;
   int wgs_per_cu;
   int use_graph;
@@ -186,10 +188,25 @@ int run_chunk(sim_batch* b, const std::vector<int>& steps, hipStream_t s) {
     d.steps = steps[i];
     d.mode = x.mode;
   }
+  // Workgroups claim tiles in entry order: the scenarios with the most agents
+  // per tile (the costliest tiles) first, so the last tiles claimed in a
+  // launch are cheap ones and its tail is short. The order decides only who
+  // takes which tile, never a result.
+  int* order = b->order.data();
+  int nused = 0;
+  for (int i = 0; i < b->capacity; ++i)
+    if (b->slots[i].used && steps[i] > 0) order[nused++] = i;
+  std::stable_sort(order, order + nused, [&](int u, int v) {
+    const HostSlot& a = b->slots[u];
+    const HostSlot& c = b->slots[v];
+    return (double)a.agents * (double)(c.S.tiles_x * c.S.tiles_y) >
+           (double)c.agents * (double)(a.S.tiles_x * a.S.tiles_y);
+  });
   for (int j = 0; j < launches; ++j) {
     int n = 0, first = 0;
-    for (int i = 0; i < b->capacity; ++i) {
-      if (!b->slots[i].used || steps[i] <= j * k) continue;
+    for (int o = 0; o < nused; ++o) {
+      const int i = order[o];
+      if (steps[i] <= j * k) continue;
       he[(size_t)j * b->capacity + n] = BatchEntry{i, first};
       first += b->slots[i].S.tiles_x * b->slots[i].S.tiles_y;
       ++n;
@@ -241,6 +258,7 @@ int sim_batch_create(int32_t capacity, void* d_workspace, size_t workspace_bytes
   b->tour = false;
   for (int i = 0; i <= kBatchMaxLaunches; ++i) b->graphs[i] = nullptr;
   b->slots.resize(capacity);
+  b->order.resize(capacity);
   hipError_t e = hipHostMalloc((void**)&b->staging, L.upload, hipHostMallocDefault);
   if (e != hipSuccess) {
     delete b;
