@@ -70,8 +70,8 @@ def algorithmic_bytes_per_step(mode: int, cells: int, agents: int) -> int:
 
 # The sources that define each traced kernel's device code.
 KERNEL_SOURCES = {
-    "tile_rows_kernel": ("tile_rows.hpp", "tile_engine.hpp", "rules.hpp"),
-    "tile_kernel": ("tile_engine.hpp", "rules.hpp"),
+    "tile_rows_kernel": ("tile_rows.hpp", "tile_engine.hpp", "rules.hpp", "step_plain.hip"),
+    "tile_kernel": ("tile_engine.hpp", "rules.hpp", "step_plain.hip"),
     "range_kernel": ("range_step.hip", "range_step.hpp", "rules.hpp"),
 }
 
