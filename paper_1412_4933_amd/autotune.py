@@ -38,7 +38,8 @@ PLAIN_CANDIDATES = [
     (1, 96, 2, 1024), (1, 128, 3, 1024), (2, 32, 2, 512), (2, 64, 2, 1024), (2, 64, 3, 1024),
     (0, 64, 2, 256), (0, 64, 3, 256), (0, 64, 4, 256), (0, 48, 2, 256), (0, 64, 3, 512),
     (0, 56, 4, 512), (0, 52, 4, 512), (0, 48, 6, 512), (0, 56, 2, 512), (0, 64, 2, 512),
-    (3, 48, 2, 256), (3, 48, 3, 256), (3, 64, 2, 256), (3, 50, 2, 256),
+    (3, 48, 2, 256), (3, 48, 3, 256), (3, 64, 2, 256), (3, 50, 2, 256), (3, 56, 3, 256), (3, 58, 3, 256),
+    (3, 60, 3, 256), (3, 62, 3, 256), (3, 56, 4, 256), (3, 60, 4, 256), (3, 60, 2, 256),
 ]
 # (nw, rows, steps per launch, threads, workgroups per CU)
 BATCH_CANDIDATES = [

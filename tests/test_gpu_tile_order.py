@@ -65,10 +65,10 @@ def test_tile_order_keeps_results(pedsim, neighbours):
 def test_tile_order_on_the_4096x2048_tiling(pedsim):
     scn = S.stress_4096x2048(S.MODE_ACO)
     sim = pedsim.Sim(scn, autotune=False)
-    sim.set_tiling(S.MODE_ACO, 3, 48, 3, 256)
+    sim.set_tiling(S.MODE_ACO, 3, 62, 3, 256)
     st = oracle.State.from_scenario(scn, threads=THREADS)
     for n in (12, 9):
-        print(f"[gpu-case] tile order: 4096x2048 ACO (3, 48, 3, 256), {n} steps", flush=True)
+        print(f"[gpu-case] tile order: 4096x2048 ACO (3, 62, 3, 256), {n} steps", flush=True)
         sim.step(n, S.MODE_ACO)
         st.run(S.MODE_ACO, n)
     same(sim, st, "4096x2048 after 21 steps")
