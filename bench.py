@@ -142,6 +142,41 @@ def cpu_baseline(workload: str, budget_s: float):
             "nproc": os.cpu_count(), "affinity_cpus": affinity}
 
 
+def stress_run(first: int = 300) -> dict:
+    """The 4096x2048 ACO workload (5% obstacles, 1M agents) beside the default
+    line: the grid whose state does not fit the caches. Its first `first`
+    steps and all of its steps, each timed from the initial state with HIP
+    events at the tiling the autotuner cache gives it, with the algorithmic
+    roofline fraction of each."""
+    import torch
+    from paper_1412_4933_amd import pedsim
+    scn = make("stress_aco_4096x2048")
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(dev)
+    alg = algorithmic_bytes_per_step(1, scn.W * scn.H, scn.agents)
+    w = pedsim.Sim(scn, stream=stream)
+    w.step(3, 1)
+    w.stats()
+    tiling = pedsim.sim_get_tiling(w.h, 1)
+    source = "autotuner cache" if 1 in w.tuned else "library default"
+    w.close()
+    out = {"workload": WORKLOADS["stress_aco_4096x2048"][1], "tiling": list(tiling), "tiling_source": source}
+    for name, K in ((f"steps_0_{first - 1}", first), ("all_steps", scn.steps)):
+        sim = pedsim.Sim(scn, stream=stream)
+        torch.cuda.synchronize(dev)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        sim.step(K, 1)
+        b.record(stream)
+        torch.cuda.synchronize(dev)
+        ms = a.elapsed_time(b)
+        sim.close()
+        gbs = alg * K / (ms / 1e3) / 1e9
+        out[name] = {"steps": K, "ms_per_step": ms / K, "agent_steps_per_s": scn.agents * K / (ms / 1e3),
+                     "alg_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def batched_run(K: int, warmup: int, autotune_first: bool = False) -> dict:
     """All 256 scenarios advanced together (one batch, captured launch
     sequences) vs the same scenarios one after another through the plain
@@ -338,6 +373,7 @@ def main():
     ap.add_argument("--quantum", type=int, default=100, help="steps per serving quantum")
     ap.add_argument("--no-serve", action="store_true", help="skip the served run of the default line")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched run of the default line")
+    ap.add_argument("--no-stress", action="store_true", help="skip the 4096x2048 run of the default line")
     ap.add_argument("--batched-steps", type=int, default=1000,
                     help="steps of the default line's batched run (the batched workload's own)")
     ap.add_argument("--tiling", default=None,
@@ -385,6 +421,12 @@ def main():
     if not args.no_batched and args.workload == "aco_1024x512":
         log(f"batched run: 256 scenarios x {args.batched_steps} steps ...")
         batched = batched_run(args.batched_steps, min(args.warmup, 20))
+
+    stress = None
+    if not args.no_stress and not args.no_batched and args.workload == "aco_1024x512":
+        log("4096x2048 ACO run ...")
+        stress = stress_run()
+        log("4096x2048:", stress)
 
     scn = make(args.workload)
     mode = scn.mode if args.workload != "stress_aco_4096x2048" else 1
@@ -512,6 +554,7 @@ def main():
         "full_run": full,
         "batched": batched,
         "served": served,
+        "stress_4096x2048": stress,
     }
     print(json.dumps(line), flush=True)
 
