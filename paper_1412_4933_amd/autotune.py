@@ -40,6 +40,8 @@ PLAIN_CANDIDATES = [
     (0, 56, 4, 512), (0, 52, 4, 512), (0, 48, 6, 512), (0, 56, 2, 512), (0, 64, 2, 512),
     (3, 48, 2, 256), (3, 48, 3, 256), (3, 64, 2, 256), (3, 50, 2, 256), (3, 56, 3, 256), (3, 58, 3, 256),
     (3, 60, 3, 256), (3, 62, 3, 256), (3, 56, 4, 256), (3, 60, 4, 256), (3, 60, 2, 256),
+    (0, 50, 5, 512), (0, 52, 5, 512), (0, 54, 5, 512), (0, 56, 5, 512), (0, 62, 5, 512), (0, 52, 6, 512),
+    (0, 56, 6, 512), (0, 48, 5, 512),
 ]
 # (nw, rows, steps per launch, threads, workgroups per CU)
 BATCH_CANDIDATES = [
