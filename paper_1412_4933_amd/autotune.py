@@ -49,7 +49,8 @@ BATCH_CANDIDATES = [
     (1, 64, 3, 512, 2), (1, 64, 2, 1024, 1), (1, 96, 3, 1024, 1), (2, 48, 2, 1024, 1),
     (0, 64, 2, 256, 2), (0, 64, 3, 256, 2), (0, 48, 2, 256, 3), (0, 64, 2, 128, 4),
     (0, 48, 3, 512, 2), (3, 48, 2, 256, 4), (3, 48, 3, 256, 4), (3, 56, 3, 256, 4), (3, 60, 3, 256, 4),
-    (3, 62, 3, 256, 4),
+    (3, 62, 3, 256, 4), (3, 62, 4, 256, 4), (3, 62, 3, 256, 5), (3, 56, 4, 256, 4), (0, 52, 5, 512, 2),
+    (0, 52, 4, 512, 2), (3, 62, 2, 256, 4),
 ]
 
 # (cols, rows, steps per launch, threads) of the range kernel (larger scanning
