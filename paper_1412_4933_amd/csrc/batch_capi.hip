@@ -99,7 +99,7 @@ namespace {
 // The eight-neighbour set runs on the row-lane engine with the pheromone in
 // LDS: two 512-thread workgroups per compute unit.
 Tiling default_batch_tiling(bool lds_form = false) {
-  static const Tiling opts[] = {{3, 62, 3, 256}, {3, 56, 3, 256}, {1, 32, 1, 256}};
+  static const Tiling opts[] = {{3, 62, 4, 256}, {3, 62, 3, 256}, {1, 32, 1, 256}};
   static const Tiling opts8[] = {{0, 48, 3, 512}, {0, 40, 2, 512}, {0, 32, 1, 256}};
   const Tiling* o = lds_form ? opts8 : opts;
   for (int i = 0; i < 3; ++i)
