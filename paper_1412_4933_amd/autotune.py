@@ -59,7 +59,8 @@ RANGE_CANDIDATES = [
     (64, 32, 1, 512), (64, 16, 1, 512), (64, 32, 1, 256), (64, 16, 1, 256), (128, 16, 1, 512),
     (32, 32, 1, 512), (64, 24, 1, 512), (64, 32, 2, 512), (64, 16, 2, 512), (64, 24, 2, 512),
     (32, 32, 2, 512), (48, 32, 2, 512), (64, 16, 3, 512), (32, 16, 3, 512), (64, 32, 2, 256),
-    (96, 16, 2, 512), (32, 32, 3, 512), (64, 8, 4, 512),
+    (96, 16, 2, 512), (32, 32, 3, 512), (64, 8, 4, 512), (64, 28, 2, 512), (56, 32, 2, 512), (80, 24, 2, 512),
+    (64, 32, 2, 448), (48, 24, 3, 512), (64, 16, 3, 256),
 ]
 
 _cache: Dict[str, tuple] = {}
