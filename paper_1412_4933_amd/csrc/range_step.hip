@@ -128,7 +128,7 @@ __device__ __forceinline__ int range_aco(const int f[5], const int d2[5], const 
 
 constexpr unsigned long long kNoClaim = ~0ull;
 constexpr int kStageBatch = 4;  // cells whose global loads a thread keeps in flight while staging
-constexpr int kCellBatch = 4;   // cells a thread takes at a time in the list and commit phases
+constexpr int kCellBatch = 2;   // cells a thread takes at a time in the list and commit phases
 
 // q = i / d for i * d < 2^32, with m = ceil(2^32 / d): one multiply-high.
 __device__ __forceinline__ uint32_t div_magic(uint32_t d) {
