@@ -722,7 +722,7 @@ __device__ bool advance_tile_rows(const Scenario& S, uint8_t* smem, int R, int k
   // every LDS read of a block is issued before its arithmetic, and each
   // cell's occupancy history is packed into bit vectors (bit u: occupied
   // after step u).
-  constexpr int kWriteRows = 4;
+  constexpr int kWriteRows = 3;
   uint32_t cnt[kTileStatFields] = {0, 0, 0, 0, 0};
   const int c = lane;
   const int gx = x0 + c;
