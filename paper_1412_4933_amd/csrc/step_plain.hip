@@ -21,11 +21,6 @@ __global__ __launch_bounds__(1024) void tile_kernel(Scenario S, int R, uint64_t 
   advance_tile<NW, MODE>(S, smem, R, tile % S.tiles_x, tile / S.tiles_x, tile, t0, steps, last != 0);
 }
 
-// On grids with more tiles than a launch runs at once, the tiles that hold
-// agents take several times longer than the empty ones, and a busy tile
-// dealt out late extends the launch. Each XCD therefore deals its tiles in the
-// order the previous launch recorded: the tiles that had agents first. The
-// order only changes which workgroup takes which tile, never the result.
 // The tile a workgroup takes (-1: none): the XCD's run of tiles in the order
 // the previous launch recorded, or in row-major order.
 __device__ __forceinline__ int pick_tile(const Scenario& S) {
