@@ -141,10 +141,10 @@ Tiling default_tiling(int mode, size_t cells, bool nb8 = false) {
   static const Tiling large_opts[] = {{3, 62, 3, 256}, {0, 48, 2, 512}, {1, 32, 1, 256}};
   static const Tiling tour_tiny[] = {{0, 48, 6, 512}, {0, 32, 4, 256}, {0, 32, 1, 256}};
   static const Tiling tour_small[] = {{0, 52, 5, 512}, {0, 52, 4, 512}, {0, 32, 1, 256}};
-  static const Tiling tour_large[] = {{0, 56, 2, 512}, {0, 48, 2, 512}, {0, 32, 1, 256}};
+  static const Tiling tour_large[] = {{0, 56, 3, 512}, {0, 56, 2, 512}, {0, 32, 1, 256}};
   static const Tiling nb8_tiny[] = {{0, 48, 6, 512}, {0, 32, 4, 256}, {0, 32, 1, 256}};
   static const Tiling nb8_small[] = {{0, 52, 5, 512}, {0, 52, 4, 512}, {0, 32, 1, 256}};
-  static const Tiling nb8_large[] = {{0, 64, 2, 512}, {0, 48, 2, 512}, {0, 32, 1, 256}};
+  static const Tiling nb8_large[] = {{0, 64, 3, 512}, {0, 64, 2, 512}, {0, 32, 1, 256}};
   const int size = cells < ((size_t)1 << 18) ? 0 : (cells < ((size_t)2 << 20) ? 1 : 2);
   const Tiling* const plain[3] = {tiny_opts, small_opts, large_opts};
   const Tiling* const tour[3] = {tour_tiny, tour_small, tour_large};
