@@ -370,7 +370,7 @@ def main():
                     help="request arrival rate (1/s); default 0.8 x the batched throughput "
                          "(9.1e9 agent-steps/s) over the mean request work (13.4M agent-steps)")
     ap.add_argument("--budget-gib", type=float, default=2.0, help="HBM budget for resident scenarios")
-    ap.add_argument("--quantum", type=int, default=100, help="steps per serving quantum")
+    ap.add_argument("--quantum", type=int, default=200, help="steps per serving quantum")
     ap.add_argument("--no-serve", action="store_true", help="skip the served run of the default line")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched run of the default line")
     ap.add_argument("--no-stress", action="store_true", help="skip the 4096x2048 run of the default line")

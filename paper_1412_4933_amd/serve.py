@@ -98,7 +98,7 @@ def poisson_requests(specs, rate: float, seed: int = 0) -> List[Request]:
 
 
 class Server:
-    def __init__(self, capacity: int = 256, budget_bytes: int = 2 << 30, quantum: int = 100,
+    def __init__(self, capacity: int = 256, budget_bytes: int = 2 << 30, quantum: int = 200,
                  device: str = "cuda", keep_state: bool = False, tuning=None):
         import torch
         self.torch = torch
